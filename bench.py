@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain spectral-TV decomposition on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--precision f32|f64]
+
+One step = one whole decomposition (K+1 ROF solves by Chambolle iterations,
+phi, S, bands, residual and the reconstruction check) of the 512 x 512
+greyscale synthetic shape image (40 disks / rectangles / ellipses, radius
+U[3,120], contrast U[-0.6,0.6], noise sigma 0.03), dt = 0.002, K = 200
+spectral samples, 300 Chambolle iterations per solve, tau = 0.248, 8 dyadic
+bands.  The image is resident in HBM before the timed region starts.
+
+Prints ONE JSON line: throughput (MPix/s), p50/p99 latency, the roofline of
+the dominant kernel (the Chambolle iteration kernel, timed live with hipEvents
+around every launch in a separate pass over the same workload) and the FP64
+CPU oracle timed on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = {
+    "workload": "512x512 greyscale synthetic shapes (40 disks/rects/ellipses), plain TV-flow "
+                "spectral decomposition",
+    "H": 512, "W": 512, "C": 1, "seed": 0,
+    "dt": 0.002, "K": 200, "inner_iters": 300, "n_bands": 8, "tau": 0.248,
+}
+# algorithmic HBM bytes of one Chambolle pixel-iteration: read px, py, g/dt,
+# write px, py (4 B each in float32, 8 B in float64)
+BYTES_PER_PIXEL_ITER = {"f32": 20, "f64": 40}
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(f, wl):
+    """Time the FP64 CPU oracle on the full workload (all host threads)."""
+    import oracle
+    edges = oracle.dyadic_edges(wl["K"], wl["n_bands"])
+    t0 = time.perf_counter()
+    oracle.decompose(f, wl["dt"], wl["K"], wl["inner_iters"], edges, tau=wl["tau"])
+    sec = time.perf_counter() - t0
+    mpix = wl["H"] * wl["W"] * wl["C"] / 1e6
+    return {"value": mpix / sec, "unit": "MPix/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "one full decomposition of the same 512x512 workload (201 ROF solves x 300 "
+                      "iterations), %.1f s" % sec}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--iters-per-launch", type=int, default=0)
+    ap.add_argument("--latency-calls", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the decomposition of one image is "
+              "not sharded across GPUs (see the sharding paragraph of the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import synth, tvspec
+
+    wl = dict(WORKLOAD)
+    wl["iters_per_launch"] = args.iters_per_launch
+    dev = torch.device("cuda:0")
+    spec = synth.IMAGE_512
+    f_host = synth.shapes_image(spec, wl["seed"])
+    f = torch.from_numpy(f_host).to(dev)
+    edges = tvspec.tvspec_dyadic_edges(wl["K"], wl["n_bands"])
+    kw = dict(tau=wl["tau"], precision=args.precision, iters_per_launch=args.iters_per_launch)
+    stream = torch.cuda.current_stream(dev)
+
+    def run(out=None):
+        return tvspec.tvspec_decompose_dev(f, wl["dt"], wl["K"], wl["inner_iters"], edges, out=out,
+                                           stream=stream, **kw)
+
+    out = run()
+    for _ in range(max(args.warmup - 1, 0)):
+        run(out)
+    torch.cuda.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+
+    # throughput: K back-to-back decompositions on one stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        run(out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    ms_per_step = wall * 1e3 / args.steps
+    stats = out["stats"].cpu().numpy()
+    print("bench: timed %d steps, %.2f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # latency: each call waited for on its own (host wall clock)
+    lat = []
+    for _ in range(args.latency_calls):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run(out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+
+    px = wl["H"] * wl["W"] * wl["C"]
+    rec = {
+        "metric": "MPix/s spectral-TV decomposition (plain vs surrogate) + p50/p99 latency",
+        "value": px / 1e6 / (ms_per_step / 1e3),
+        "unit": "MPix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": wl,
+        "path": "plain",
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "calls": len(lat),
+                       "device_p50": percentile(step_ms, 50), "device_p99": percentile(step_ms, 99)},
+        "report": {"recon_err": float(stats[0]), "mean_err": float(stats[1]), "nonfinite": float(stats[2])},
+    }
+
+    if not args.no_roofline:
+        tvspec.tvspec_timing_enable(True)
+        try:
+            run(out)
+            torch.cuda.synchronize()
+            t = tvspec.tvspec_timing_read()
+        finally:
+            tvspec.tvspec_timing_enable(False)
+        avg_ms = t["kernel_ms"] / t["launches"]
+        per_launch_bytes = BYTES_PER_PIXEL_ITER[args.precision] * t["pixel_iters"] / t["launches"]
+        achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
+        rec["roofline"] = {
+            "kernel": "k_chambolle_tile",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+            "launches_per_step": t["launches"],
+            "bytes_per_launch": per_launch_bytes,
+            "kernel_share_of_step": t["kernel_ms"] / ms_per_step,
+        }
+        print("bench: roofline pass done", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on the same workload ...", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(f_host, wl)
+
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

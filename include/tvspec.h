@@ -1,0 +1,156 @@
+/*
+ * tvspec -- spectral total-variation decomposition on one AMD MI355X (gfx950).
+ *
+ * The method is that of Grossmann, Korolev, Gilboa, Schoenlieb, "Deeply
+ * Learned Spectral Total Variation Decomposition" (arXiv 2006.10004):
+ *
+ *   TV flow, Sec. 2.1 Eq. (1):      u_t = -p, p in dJ(u), u(0) = f, with J the
+ *                                   isotropic TV of Eq. (2);
+ *   implicit Euler, Sec. 2.2 Eq. (8): u_{s+1} = argmin_v 0.5||u_s - v||^2
+ *                                   + dt J(v), one ROF problem per step, solved
+ *                                   by Chambolle's dual projection iteration
+ *                                   (the solver Sec. 4.3 names);
+ *   TV transform, Eq. (3):          phi(t) = t u_tt(t), on t_k = k dt by the
+ *                                   central second difference;
+ *   spectrum (display after Eq. (3)): S(t_k) = ||phi(t_k)||_1;
+ *   bands, Eq. (7):                 b_j = integral of phi over (t_{e_{j-1}}, t_{e_j}];
+ *   residual, Eq. (5):              f_r(T) = u(T) - T u_t(T), T = K dt,
+ *                                   so that f = sum_j b_j + f_r.
+ *
+ * Discretisation (the paper only says "finite differences"): forward
+ * differences with Neumann boundary for the gradient, the negative adjoint
+ * for the divergence, isotropic pointwise norm; Chambolle's semi-implicit
+ * update  p <- (p + tau grad w) / (1 + tau |grad w|),  w = div p - g/dt,
+ * v = g - dt div p.  The dual field p is warm-started from the previous
+ * solve by default.  K counts spectral samples phi_1..phi_K, which takes K+1
+ * ROF solves (u_1..u_{K+1}).  Band edges are step indices
+ * 0 = e_0 < e_1 < ... < e_B = K; band j holds the samples e_{j-1} < k <= e_j.
+ * The residual is returned on its own (the paper adds it to the last band).
+ *
+ * Layouts (row-major, column index fastest):
+ *   f         [C][H][W]  float32
+ *   bands     [n_bands][C][H][W]  float64
+ *   S         [C][K]     float64,  S[c][k-1] = S_c(t_k)
+ *   residual  [C][H][W]  float64
+ * Channels are independent decompositions.
+ *
+ * Precision: the inner Chambolle iterations run in float32
+ * (TVSPEC_PRECISION_F32, the default) or float64 (TVSPEC_PRECISION_F64).
+ * The flow state u, its step differences, phi, the bands, S and the
+ * reconstruction check are always float64.
+ *
+ * Threading: calls on one device share that device's scratch memory; calls
+ * that overlap in time on one device (different host threads, or different
+ * streams) race.  Serialise them (one stream, or one thread).
+ */
+#ifndef TVSPEC_H
+#define TVSPEC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define TVSPEC_OK 0
+#define TVSPEC_EINVAL (-1)   /* invalid argument; nothing was done on the device */
+#define TVSPEC_ENUMERIC (-2) /* non-finite input value (host entry point only) */
+#define TVSPEC_ENOMEM (-3)   /* device or host allocation failed */
+#define TVSPEC_EDEVICE (-4)  /* HIP runtime error; tvspec_last_error() has the text */
+
+#define TVSPEC_PRECISION_F32 0
+#define TVSPEC_PRECISION_F64 1
+
+#define TVSPEC_DEFAULT_TAU 0.248
+
+/* Number of doubles tvspec_decompose_dev writes to its stats buffer. */
+#define TVSPEC_NSTATS 4
+
+/*
+ * Host entry point: decompose a C x H x W float32 image held in host memory.
+ * Synchronous.  The caller owns and allocates every buffer (sizes above);
+ * the library keeps no pointer after return.  Defaults: tau = 0.248, warm
+ * start, float32 inner iterations, automatic temporal blocking.
+ *
+ *   dt           time step of the flow (> 0, finite)
+ *   K            number of spectral samples (>= 1); K+1 ROF solves are run
+ *   inner_iters  Chambolle iterations per ROF solve (>= 1)
+ *   band_edges   n_bands+1 step indices, 0 = e_0 < ... < e_B = K
+ *
+ * Errors: TVSPEC_EINVAL for H < 2, W < 2, C < 1, H*W > 2^30, bad dt, K,
+ * inner_iters, n_bands, edges or a null pointer; TVSPEC_ENUMERIC if f holds
+ * a NaN or infinity (checked on the host before any device work);
+ * TVSPEC_ENOMEM; TVSPEC_EDEVICE.  Outputs are unspecified on error.
+ */
+int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
+                     const int *band_edges, int n_bands, double *bands, double *S,
+                     double *residual);
+
+/*
+ * Device entry point with all options.  f, bands, S, residual and stats are
+ * DEVICE pointers (e.g. torch tensors' data_ptr()); band_edges is a HOST
+ * array.  The work is enqueued on `stream` (a hipStream_t; NULL = the null
+ * stream) and the call returns without waiting; the caller keeps every
+ * buffer alive until the stream has completed it.
+ *
+ *   tau               Chambolle step, 0 < tau <= 0.25 (Chambolle's theorem
+ *                     asks tau <= 1/8; up to 1/4 converges in practice)
+ *   warm_start        1: the dual field carries over between ROF solves;
+ *                     0: it restarts from zero at every solve
+ *   precision         TVSPEC_PRECISION_F32 or TVSPEC_PRECISION_F64
+ *   iters_per_launch  temporal blocking factor: Chambolle iterations done per
+ *                     kernel launch on an LDS-resident tile (0 = automatic,
+ *                     else 1..16 for F32, 1..8 for F64).  Results do not
+ *                     depend on it: every variant applies the same per-pixel
+ *                     arithmetic in the same order.
+ *   stats             TVSPEC_NSTATS doubles (device): [0] max |f - sum of
+ *                     bands - residual|, [1] max over channels of
+ *                     |mean(u_{K+1}) - mean(f_c)|, [2] number of non-finite
+ *                     values found in f (the outputs are then meaningless),
+ *                     [3] reserved (0).
+ *
+ * Errors: as tvspec_decompose, except that non-finite input is reported in
+ * stats[2] instead of a return code.  Argument validation happens before any
+ * device work.
+ */
+int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
+                         int inner_iters, const int *band_edges, int n_bands, double *bands,
+                         double *S, double *residual, double *stats, double tau, int warm_start,
+                         int precision, int iters_per_launch, void *stream);
+
+/*
+ * Dyadic band edges (the paper groups unit-step bands dyadically, Sec. 4.1):
+ * edges = {0, 1, 2, 4, ..., 2^(B-2), K} for B = n_bands >= 2, {0, K} for
+ * B = 1.  `edges` has room for n_bands+1 ints (host memory).
+ * Errors: TVSPEC_EINVAL if K < 1, n_bands < 1, edges is NULL, or
+ * 2^(B-2) >= K.
+ */
+int tvspec_dyadic_edges(int K, int n_bands, int *edges);
+
+/*
+ * Kernel timing for benchmarks.  While enabled (on = 1), every launch of the
+ * Chambolle iteration kernel is bracketed by a pair of hipEvents recorded on
+ * its launch stream.  tvspec_timing_read() waits for the recorded events,
+ * returns the summed kernel time (ms), the number of launches and the number
+ * of pixel-iterations (pixels x Chambolle iterations) they performed, and
+ * clears the record.  Any pointer may be NULL.  Enabling adds a little host
+ * work per launch; leave it off for throughput runs.
+ * Errors: TVSPEC_EDEVICE (event creation, query or timing failed).
+ */
+int tvspec_timing_enable(int on);
+int tvspec_timing_read(double *kernel_ms, long long *launches, long long *pixel_iters);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *tvspec_last_error(void);
+
+/* Library version string. */
+const char *tvspec_version(void);
+
+/* Free every device buffer the library caches.  Must not overlap a call in
+ * flight on any stream. */
+void tvspec_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVSPEC_H */

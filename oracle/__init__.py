@@ -46,6 +46,8 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     i, d = ctypes.c_int, ctypes.c_double
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = i
     lib.orc_grad.argtypes = [_dp, i, i, _dp, _dp]
     lib.orc_grad.restype = None
     lib.orc_div.argtypes = [_dp, _dp, i, i, _dp]
@@ -64,6 +66,11 @@ def _load():
     lib.orc_decompose.restype = i
     _lib = lib
     return lib
+
+
+def num_threads():
+    """Threads the oracle's per-pixel loops run on."""
+    return int(_load().orc_num_threads())
 
 
 def _plane(a):

@@ -40,8 +40,21 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IDX(i, j) ((size_t)(i) * (size_t)W + (size_t)(j))
+
+/* Number of threads the per-pixel loops use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Forward-difference gradient with Neumann boundary:
  *   gx(i,j) = u(i,j+1) - u(i,j) for j < W-1, and 0 on the last column;

@@ -1,0 +1,187 @@
+"""Python binding of the tvspec C ABI (include/tvspec.h).
+
+Argument marshalling only: every step of the decomposition runs in the HIP
+kernels of libtvspec.so.  There is no CPU fallback; if the library is not
+built, importing this module raises.
+
+torch is imported before the library is loaded so that the library binds to
+the HIP runtime torch has already loaded (one runtime per process); torch is
+used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtvspec.so")
+
+TVSPEC_OK = 0
+TVSPEC_EINVAL = -1
+TVSPEC_ENUMERIC = -2
+TVSPEC_ENOMEM = -3
+TVSPEC_EDEVICE = -4
+TVSPEC_PRECISION_F32 = 0
+TVSPEC_PRECISION_F64 = 1
+TVSPEC_DEFAULT_TAU = 0.248
+TVSPEC_NSTATS = 4
+
+EXPORTS = (
+    "tvspec_decompose",
+    "tvspec_decompose_dev",
+    "tvspec_dyadic_edges",
+    "tvspec_timing_enable",
+    "tvspec_timing_read",
+    "tvspec_last_error",
+    "tvspec_version",
+    "tvspec_release",
+)
+
+
+class TvspecError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("tvspec error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("%s is not built (python -m paper_2006_10004_amd.build)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i, d, vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    lib.tvspec_decompose.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp]
+    lib.tvspec_decompose.restype = i
+    lib.tvspec_decompose_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, i, i, i, vp]
+    lib.tvspec_decompose_dev.restype = i
+    lib.tvspec_dyadic_edges.argtypes = [i, i, vp]
+    lib.tvspec_dyadic_edges.restype = i
+    lib.tvspec_timing_enable.argtypes = [i]
+    lib.tvspec_timing_enable.restype = i
+    lib.tvspec_timing_read.argtypes = [vp, vp, vp]
+    lib.tvspec_timing_read.restype = i
+    lib.tvspec_last_error.argtypes = []
+    lib.tvspec_last_error.restype = ctypes.c_char_p
+    lib.tvspec_version.argtypes = []
+    lib.tvspec_version.restype = ctypes.c_char_p
+    lib.tvspec_release.argtypes = []
+    lib.tvspec_release.restype = None
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != TVSPEC_OK:
+        raise TvspecError(rc, tvspec_last_error())
+
+
+def tvspec_last_error() -> str:
+    return _lib.tvspec_last_error().decode()
+
+
+def tvspec_version() -> str:
+    return _lib.tvspec_version().decode()
+
+
+def tvspec_release() -> None:
+    _lib.tvspec_release()
+
+
+def tvspec_timing_enable(on: bool) -> None:
+    """Bracket every Chambolle kernel launch with hipEvents (benchmarks)."""
+    _check(_lib.tvspec_timing_enable(1 if on else 0))
+
+
+def tvspec_timing_read() -> dict:
+    """Wait for the recorded launches; return and clear their summed kernel
+    time (ms), launch count and pixel-iterations."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_longlong(0)
+    pit = ctypes.c_longlong(0)
+    _check(_lib.tvspec_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pit)))
+    return {"kernel_ms": ms.value, "launches": n.value, "pixel_iters": pit.value}
+
+
+def tvspec_dyadic_edges(K: int, n_bands: int) -> list:
+    """{0, 1, 2, 4, ..., 2^(B-2), K} (B = n_bands >= 2) or {0, K}."""
+    e = (ctypes.c_int * (max(n_bands, 0) + 1))()
+    _check(_lib.tvspec_dyadic_edges(int(K), int(n_bands), e))
+    return list(e)
+
+
+def _edges_array(edges):
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32))
+    if e.ndim != 1 or e.size < 2:
+        raise ValueError("band_edges must be a 1-D sequence of n_bands+1 ints")
+    return e
+
+
+def tvspec_decompose(f: np.ndarray, dt: float, K: int, inner_iters: int, band_edges):
+    """Host entry point (synchronous, default options).
+
+    f: (C,H,W) or (H,W) float32 numpy array.  Returns dict of numpy arrays
+    bands (B,C,H,W), S (C,K), residual (C,H,W)."""
+    f = np.asarray(f)
+    if f.ndim == 2:
+        f = f[None]
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    C, H, W = f.shape
+    e = _edges_array(band_edges)
+    B = e.size - 1
+    bands = np.empty((B, C, H, W), dtype=np.float64)
+    S = np.empty((C, K), dtype=np.float64)
+    res = np.empty((C, H, W), dtype=np.float64)
+    _check(_lib.tvspec_decompose(f.ctypes.data, H, W, C, float(dt), int(K), int(inner_iters),
+                                 e.ctypes.data, B, bands.ctypes.data, S.ctypes.data, res.ctypes.data))
+    return {"bands": bands, "S": S, "residual": res}
+
+
+def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges,
+                         tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = True,
+                         precision: str = "f32", iters_per_launch: int = 0,
+                         stream: torch.cuda.Stream | None = None, out: dict | None = None):
+    """Device entry point: f is a (C,H,W) or (H,W) float32 tensor on a GPU.
+
+    Enqueues on `stream` (default: torch's current stream) and returns
+    without waiting.  Returns dict of device tensors bands (B,C,H,W), S (C,K),
+    residual (C,H,W) and stats (4,) = [recon_err, mean_err, n_nonfinite, 0].
+    `out` may pass preallocated tensors of those shapes."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda:
+        raise TypeError("f must be a GPU tensor")
+    if f.dtype != torch.float32:
+        raise TypeError("f must be float32")
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    if f.dim() != 3:
+        raise ValueError("f must be (C,H,W) or (H,W)")
+    f = f.contiguous()
+    C, H, W = f.shape
+    e = _edges_array(band_edges)
+    B = e.size - 1
+    prec = {"f32": TVSPEC_PRECISION_F32, "f64": TVSPEC_PRECISION_F64}[precision]
+    dev = f.device
+    if out is None:
+        out = {
+            "bands": torch.empty((B, C, H, W), dtype=torch.float64, device=dev),
+            "S": torch.empty((C, K), dtype=torch.float64, device=dev),
+            "residual": torch.empty((C, H, W), dtype=torch.float64, device=dev),
+            "stats": torch.empty((TVSPEC_NSTATS,), dtype=torch.float64, device=dev),
+        }
+    else:
+        want = {"bands": (B, C, H, W), "S": (C, K), "residual": (C, H, W), "stats": (TVSPEC_NSTATS,)}
+        for k, shp in want.items():
+            t = out[k]
+            if tuple(t.shape) != shp or t.dtype != torch.float64 or t.device != dev or not t.is_contiguous():
+                raise ValueError("out[%r] must be a contiguous float64 %s tensor on %s" % (k, shp, dev))
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(_lib.tvspec_decompose_dev(
+            f.data_ptr(), H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
+            out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
+            out["stats"].data_ptr(), float(tau), 1 if warm_start else 0, prec,
+            int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
+    return out

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/tvspec.h declares, and rejects invalid arguments before any device
+work; the product path does not reach the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvspec.h")
+LIB = os.path.join(ROOT, "paper_2006_10004_amd", "libtvspec.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tvspec_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def tv():
+    from paper_2006_10004_amd import tvspec
+    return tvspec
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(LIB)
+    names = declared()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header(tv):
+    assert sorted(tv.EXPORTS) == declared()
+    for n in declared():
+        assert callable(getattr(tv, n))
+
+
+def test_version(tv):
+    assert "gfx950" in tv.tvspec_version()
+
+
+def test_dyadic_edges(tv):
+    assert tv.tvspec_dyadic_edges(50, 6) == [0, 1, 2, 4, 8, 16, 50]
+    assert tv.tvspec_dyadic_edges(60, 4) == [0, 1, 2, 4, 60]
+    assert tv.tvspec_dyadic_edges(200, 8) == [0, 1, 2, 4, 8, 16, 32, 64, 200]
+    assert tv.tvspec_dyadic_edges(5, 1) == [0, 5]
+    for K, B in ((4, 5), (0, 2), (8, 0)):
+        with pytest.raises(tv.TvspecError) as ei:
+            tv.tvspec_dyadic_edges(K, B)
+        assert ei.value.code == tv.TVSPEC_EINVAL
+
+
+BAD = [
+    dict(H=1), dict(W=1), dict(C=0), dict(dt=0.0), dict(dt=float("nan")), dict(dt=float("inf")),
+    dict(K=0), dict(iters=0), dict(edges=[0, 2, 2, 4]), dict(edges=[1, 4]), dict(edges=[0, 3]),
+    dict(nb=0), dict(nb=5), dict(H=1 << 16, W=1 << 16),
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_host_entry_validation(bad):
+    """Invalid arguments return TVSPEC_EINVAL before any device call (so this
+    runs on a machine without a GPU)."""
+    lib = ctypes.CDLL(LIB)
+    a = dict(H=4, W=5, C=1, dt=0.1, K=4, iters=3, edges=[0, 1, 4], nb=None)
+    a.update(bad)
+    e = np.array(a["edges"], dtype=np.int32)
+    nb = len(e) - 1 if a["nb"] is None else a["nb"]
+    f = np.zeros(16, np.float32)
+    out = np.zeros(64, np.float64)
+    lib.tvspec_decompose.restype = ctypes.c_int
+    rc = lib.tvspec_decompose(f.ctypes.data_as(ctypes.c_void_p), a["H"], a["W"], a["C"],
+                              ctypes.c_double(a["dt"]), a["K"], a["iters"],
+                              e.ctypes.data_as(ctypes.c_void_p), nb,
+                              out.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p),
+                              out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == -1
+
+
+def test_host_entry_null_pointer_and_nonfinite(tv):
+    lib = ctypes.CDLL(LIB)
+    e = np.array([0, 2], dtype=np.int32)
+    out = np.zeros(64, np.float64)
+    rc = lib.tvspec_decompose(None, 3, 3, 1, ctypes.c_double(0.1), 2, 3, e.ctypes.data_as(ctypes.c_void_p), 1,
+                              out.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p),
+                              out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == -1
+    f = np.zeros((3, 3), np.float32)
+    f[1, 1] = np.inf
+    with pytest.raises(tv.TvspecError) as ei:
+        tv.tvspec_decompose(f, 0.1, 2, 3, [0, 2])
+    assert ei.value.code == tv.TVSPEC_ENUMERIC
+    assert "NaN" in tv.tvspec_last_error() or "infinity" in tv.tvspec_last_error()
+
+
+def test_device_entry_validation_options():
+    """Option checks of the device entry point also run before device work."""
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.tvspec_decompose_dev.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, vp,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    e = np.array([0, 4], dtype=np.int32)
+    fake = vp(0x1000)  # never dereferenced: validation fails first
+    base = dict(tau=0.248, warm=1, prec=0, ipl=0)
+    for bad in (dict(tau=0.0), dict(tau=0.26), dict(warm=2), dict(prec=2), dict(ipl=-1), dict(ipl=17),
+                dict(prec=1, ipl=9)):
+        a = dict(base)
+        a.update(bad)
+        rc = lib.tvspec_decompose_dev(fake, 8, 8, 1, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake, fake, fake,
+                                      a["tau"], a["warm"], a["prec"], a["ipl"], None)
+        assert rc == -1, bad
+    rc = lib.tvspec_decompose_dev(fake, 8, 8, 1, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake, fake, None,
+                                  0.248, 1, 0, 0, None)
+    assert rc == -1
+
+
+def test_product_path_never_reaches_the_oracle():
+    """No module of the package, nor the HIP source, imports or links the
+    oracle; there is no CPU fallback."""
+    pkg = os.path.join(ROOT, "paper_2006_10004_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", text, flags=re.M), fn
+                assert "liboracle" not in text and "orc_" not in text, fn
