@@ -119,8 +119,10 @@ def rof(g, lam, iters, tau=DEFAULT_TAU, px=None, py=None):
     return v, px, py
 
 
-def tv_flow(f, dt, nsteps, iters, tau=DEFAULT_TAU, warm=True):
-    """States u_0..u_nsteps of the implicit-Euler TV flow, shape (nsteps+1, H, W)."""
+def tv_flow(f, dt, nsteps, iters, tau=DEFAULT_TAU, warm=False):
+    """States u_0..u_nsteps of the implicit-Euler TV flow, shape (nsteps+1, H, W).
+
+    warm=False (default): every ROF solve starts its dual field at zero."""
     f = _plane(f)
     H, W = f.shape
     states = np.empty((nsteps + 1, H, W), dtype=np.float64)
@@ -150,8 +152,11 @@ def spectral(states, dt, K, edges, want_phi=False):
     return {"S": S, "bands": bands, "residual": res, "phi": phi}
 
 
-def decompose(f, dt, K, iters, edges, tau=DEFAULT_TAU, warm=True):
+def decompose(f, dt, K, iters, edges, tau=DEFAULT_TAU, warm=False):
     """Full decomposition of a (C,H,W) or (H,W) float32 image.
+
+    warm=False (default): every ROF solve starts its dual field at zero (the
+    paper does not say how the dual field is initialised; see tv_flow).
 
     Returns dict(bands (B,C,H,W), S (C,K), residual (C,H,W), recon_err, mean_err)."""
     f = np.asarray(f)

@@ -161,8 +161,9 @@ void orc_rof(const double *g, int H, int W, double lambda, double tau, int iters
 
 /* TV flow Eq. (1) by implicit Euler: u_0 = f, u_{s+1} = ROF(u_s, dt) for
  * s = 0..nsteps-1.  states receives u_0..u_nsteps, (nsteps+1) planes of H*W.
- * warm != 0: the dual field of solve s starts from the final one of solve
- * s-1 (zero for s = 0); warm == 0: every solve starts from zero. */
+ * warm == 0: every solve starts its dual field from zero; warm != 0: the
+ * dual field of solve s starts from the final one of solve s-1 (zero for
+ * s = 0).  The paper does not say which; both are offered. */
 void orc_tv_flow(const double *f, int H, int W, double dt, int nsteps, int iters,
                  double tau, int warm, double *states)
 {

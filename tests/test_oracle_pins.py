@@ -252,10 +252,12 @@ C1 = dict(dt=0.005, K=60, iters=200, edges=[0, 1, 2, 4, 60])
 def test_half_plane_single_spike(orc):
     """A step is a TV eigenfunction: its flow decays linearly and vanishes at
     T* = c a b / (a + b).  With T* = 8 dt: phi_8 dt = f - mean(f), all other
-    phi = 0, S(t_8) = sum |f - mean| / dt = 48, residual = mean(f)."""
+    phi = 0, S(t_8) = sum |f - mean| / dt = 48, residual = mean(f).  (Warm
+    start: the solve that ends exactly at extinction is the critical case of
+    the ROF problem, which a zero start reaches only like 1/N.)"""
     f = synth.step_image(3, 4, 6, 1.0)
-    r = orc.decompose(f, 0.3, 10, 2000, [0, 1, 2, 4, 8, 10])
-    fm = f[0].astype(np.float64) - 0.4
+    r = orc.decompose(f, 0.3, 10, 2000, [0, 1, 2, 4, 8, 10], warm=True)
+    fm = f.astype(np.float64) - 0.4
     b = r["bands"][:, 0]
     assert np.abs(b[3] - fm).max() < 1e-12
     for j in (0, 1, 2, 4):
@@ -263,6 +265,31 @@ def test_half_plane_single_spike(orc):
     assert np.abs(r["residual"][0] - 0.4).max() < 1e-12
     assert abs(r["S"][0, 7] - 48.0) < 1e-10
     assert np.all(np.delete(r["S"][0], 7) < 1e-10)
+
+
+def half_plane_flow(f, mean, t_ext, t):
+    """Exact flow of the step image: linear decay to the mean at t_ext."""
+    return mean + (f - mean) * max(0.0, 1.0 - t / t_ext)
+
+
+def test_half_plane_two_samples_cold_start(orc):
+    """Extinction strictly inside a step (T* / dt = 6.86): the exact flow puts
+    phi on the two samples around it; every ROF solve is non-critical, so a
+    cold-started Chambolle iteration reaches the closed form."""
+    f = synth.step_image(3, 4, 6, 1.0)
+    f64 = f.astype(np.float64)
+    dt, K, t_ext = 0.35, 10, 2.4
+    edges = [0, 1, 2, 4, 8, 10]
+    u = [half_plane_flow(f64, 0.4, t_ext, k * dt) for k in range(K + 2)]
+    phidt = [k * (u[k - 1] - 2 * u[k] + u[k + 1]) for k in range(1, K + 1)]
+    r = orc.decompose(f, dt, K, 10000, edges)
+    for j in range(5):
+        want = sum(phidt[k - 1] for k in range(edges[j] + 1, edges[j + 1] + 1))
+        assert np.abs(r["bands"][j, 0] - want).max() < 1e-12
+    assert np.abs(r["residual"][0] - (u[K] + K * (u[K] - u[K + 1]))).max() < 1e-12
+    S_want = np.array([np.abs(p).sum() / dt for p in phidt])
+    assert np.abs(r["S"][0] - S_want).max() < 1e-9
+    assert S_want[5] > 1 and S_want[6] > 1  # phi sits on samples 6 and 7
 
 
 def test_constant_image(orc):
