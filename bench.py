@@ -31,9 +31,13 @@ WORKLOAD = {
     "H": 512, "W": 512, "C": 1, "seed": 0,
     "dt": 0.002, "K": 200, "inner_iters": 300, "n_bands": 8, "tau": 0.248,
 }
-# algorithmic HBM bytes of one Chambolle pixel-iteration: read px, py, g/dt,
-# write px, py (4 B each in float32, 8 B in float64)
-BYTES_PER_PIXEL_ITER = {"f32": 20, "f64": 40}
+# algorithmic HBM bytes of one Chambolle pixel-iteration: read the dual field
+# (px, py) and the data term G = grad(g)/dt (Gx, Gy), write (px, py); the
+# dual field is float32 in F32 and float64 in MIXED and F64, G is float32 in
+# F32 and MIXED and float64 in F64
+BYTES_PER_PIXEL_ITER = {"f32": 24, "mixed": 40, "f64": 48}
+# arithmetic type of the path, per precision mode
+DTYPE = {"f32": "f32", "mixed": "f64 (f32-seeded sqrt/rcp)", "f64": "f64"}
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
@@ -65,7 +69,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="mixed", choices=["f32", "mixed", "f64"])
     ap.add_argument("--iters-per-launch", type=int, default=0)
     ap.add_argument("--latency-calls", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,6 +89,8 @@ def main():
 
     wl = dict(WORKLOAD)
     wl["iters_per_launch"] = args.iters_per_launch
+    wl["precision"] = args.precision
+    wl["warm_start"] = False
     dev = torch.device("cuda:0")
     spec = synth.IMAGE_512
     f_host = synth.shapes_image(spec, wl["seed"])
@@ -139,7 +145,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": wl,
         "path": "plain",

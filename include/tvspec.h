@@ -21,8 +21,8 @@
  * differences with Neumann boundary for the gradient, the negative adjoint
  * for the divergence, isotropic pointwise norm; Chambolle's semi-implicit
  * update  p <- (p + tau grad w) / (1 + tau |grad w|),  w = div p - g/dt,
- * v = g - dt div p.  The dual field p is warm-started from the previous
- * solve by default.  K counts spectral samples phi_1..phi_K, which takes K+1
+ * v = g - dt div p.  Every ROF solve starts from p = 0 by default (cold
+ * start; see warm_start below).  K counts spectral samples phi_1..phi_K, which takes K+1
  * ROF solves (u_1..u_{K+1}).  Band edges are step indices
  * 0 = e_0 < e_1 < ... < e_B = K; band j holds the samples e_{j-1} < k <= e_j.
  * The residual is returned on its own (the paper adds it to the last band).
@@ -34,10 +34,9 @@
  *   residual  [C][H][W]  float64
  * Channels are independent decompositions.
  *
- * Precision: the inner Chambolle iterations run in float32
- * (TVSPEC_PRECISION_F32, the default) or float64 (TVSPEC_PRECISION_F64).
- * The flow state u, its step differences, phi, the bands, S and the
- * reconstruction check are always float64.
+ * Precision: the inner Chambolle iterations run in one of the modes
+ * TVSPEC_PRECISION_* below.  The flow state u, its step differences, phi,
+ * the bands, S and the reconstruction check are always float64.
  *
  * Threading: calls on one device share that device's scratch memory; calls
  * that overlap in time on one device (different host threads, or different
@@ -57,8 +56,19 @@ extern "C" {
 #define TVSPEC_ENOMEM (-3)   /* device or host allocation failed */
 #define TVSPEC_EDEVICE (-4)  /* HIP runtime error; tvspec_last_error() has the text */
 
+/* Precision of the inner Chambolle iteration:
+ *   F32    float32 dual field and arithmetic (fastest; on long flows its
+ *          rounding moves the bands by more than 2e-4, e.g. ~4.5e-4 on a
+ *          512x512 image with dt = 0.002, K = 200, 300 iterations)
+ *   F64    IEEE float64 dual field and arithmetic
+ *   MIXED  float64 dual field and arithmetic; |grad w| and the reciprocal
+ *          from float32 hardware estimates refined by one float64 Newton
+ *          step; grad(g)/dt stored in float32.  Float64-level results
+ *          (~3e-6 on the workload above) at less cost than F64.  Default. */
 #define TVSPEC_PRECISION_F32 0
 #define TVSPEC_PRECISION_F64 1
+#define TVSPEC_PRECISION_MIXED 2
+#define TVSPEC_DEFAULT_PRECISION TVSPEC_PRECISION_MIXED
 
 #define TVSPEC_DEFAULT_TAU 0.248
 
@@ -68,8 +78,8 @@ extern "C" {
 /*
  * Host entry point: decompose a C x H x W float32 image held in host memory.
  * Synchronous.  The caller owns and allocates every buffer (sizes above);
- * the library keeps no pointer after return.  Defaults: tau = 0.248, warm
- * start, float32 inner iterations, automatic temporal blocking.
+ * the library keeps no pointer after return.  Defaults: tau = 0.248, cold
+ * start, TVSPEC_DEFAULT_PRECISION, automatic temporal blocking.
  *
  *   dt           time step of the flow (> 0, finite)
  *   K            number of spectral samples (>= 1); K+1 ROF solves are run
@@ -94,12 +104,19 @@ int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int 
  *
  *   tau               Chambolle step, 0 < tau <= 0.25 (Chambolle's theorem
  *                     asks tau <= 1/8; up to 1/4 converges in practice)
- *   warm_start        1: the dual field carries over between ROF solves;
- *                     0: it restarts from zero at every solve
- *   precision         TVSPEC_PRECISION_F32 or TVSPEC_PRECISION_F64
+ *   warm_start        0 (default of tvspec_decompose): every ROF solve
+ *                     starts its dual field from zero; 1: the dual field
+ *                     carries over from the previous solve.  The paper does
+ *                     not say which.  Warm starting converges each solve
+ *                     further for the same inner_iters, but the dual field
+ *                     is not unique and drifts from solve to solve: over
+ *                     long flows (200 steps of 300 iterations on 512x512)
+ *                     the result then changes by ~1e-3 under a one-ulp
+ *                     change of one input pixel, against ~3e-7 cold.
+ *   precision         TVSPEC_PRECISION_F32, _F64 or _MIXED
  *   iters_per_launch  temporal blocking factor: Chambolle iterations done per
  *                     kernel launch on an LDS-resident tile (0 = automatic,
- *                     else 1..16 for F32, 1..8 for F64).  Results do not
+ *                     else 1..16 for F32, 1..8 for F64 and MIXED).  Results do not
  *                     depend on it: every variant applies the same per-pixel
  *                     arithmetic in the same order.
  *   stats             TVSPEC_NSTATS doubles (device): [0] max |f - sum of

@@ -9,24 +9,43 @@
 //                      Eq. (7) and the residual of Eq. (5).
 //
 // Device work per decomposition (one C x H x W image, channels independent):
-//   k_init           u_0 = f (float64), g/dt for the first solve, p = 0,
-//                    bands = 0, count of non-finite inputs;
+//   k_init           u_0 = f (float64), G = grad(f)/dt for the first solve,
+//                    p = 0, bands = 0, count of non-finite inputs;
 //   k_chambolle_tile the hot loop.  Each launch runs `iters` (<= TB) Jacobi
 //                    iterations of Chambolle's fixed point on a 32x32 output
-//                    tile whose (32+2TB)^2 neighbourhood is staged once in LDS;
-//                    the dual field stays in registers, only the neighbour
-//                    values cross lanes through LDS.  Tiles are mapped to
-//                    workgroups so that each XCD works on one horizontal band
-//                    of the image (neighbouring halos then hit the same L2);
+//                    tile whose (32+2TB)^2 neighbourhood is staged once; the
+//                    dual field stays in registers, only neighbour values
+//                    cross lanes through LDS.  Tiles are mapped to workgroups
+//                    so that each XCD works on one horizontal band of the
+//                    image (neighbouring halos then hit the same L2);
 //   k_flow_step      one launch per ROF solve, fused: div p, u_{s+1} =
 //                    u_s - dt div p, D_s = dt div p, phi_s dt = s (D_{s-1} -
 //                    D_s) added to its band, a per-block partial of sum |D_{s-1}
-//                    - D_s| for S(t_s), the residual at s = K, and g/dt of the
-//                    next solve.  u_{s-1}, u_s, u_{s+1} never exist as planes;
+//                    - D_s| for S(t_s), the residual at s = K, and grad(g)/dt
+//                    of the next solve.  u_{s-1} and u_{s+1} never exist as
+//                    planes beside u_s;
 //   k_check          per-block partials of the reconstruction error and of
 //                    the mean of u_{K+1} and f;
-//   k_reduce         one block: S(t_k) and the report, in a fixed order
-//                    (results are bit-reproducible run to run).
+//   k_reduce_s       S(t_k) from the step partials, one block per (k, c);
+//   k_report         the report (reductions in a fixed order, so results are
+//                    bit-reproducible run to run).
+//
+// Precision modes of the inner iteration.  S is the type of the dual field
+// and of the update arithmetic, M the type G is stored in:
+//   F32    S = float,  M = float   (IEEE-rounded float32 except the
+//          hardware square root and reciprocal estimates)
+//   F64    S = double, M = double  (IEEE float64 throughout)
+//   MIXED  S = double, M = float.  float64 arithmetic, but |a| and the
+//          reciprocal come from the float32 hardware estimates refined by one
+//          float64 Newton step, and G is stored in float32.  On gfx950, with
+//          packed float32 math off, float64 add and fma issue at the float32
+//          rate; what makes float64 dear is its square root and division
+//          sequences, which this avoids.  Float32 is not enough for long
+//          flows: with dt = 0.002 and 200 steps the spectral sums weight
+//          differences of the flow by up to 200, and the float32 rounding of
+//          div p (a cancelling difference of O(1) values) and of the update's
+//          nonlinear factor then moves the bands by ~4e-4.
+// The flow state u, D, phi, the bands, S and the checks are float64 always.
 //
 // Arithmetic contract: every kernel variant (any temporal blocking factor)
 // applies the same per-pixel operations in the same order, so results do not
@@ -42,11 +61,12 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "tvspec.h"
 
-#define TVSPEC_VERSION_STRING "tvspec 0.1.0 (gfx950)"
+#define TVSPEC_VERSION_STRING "tvspec 0.2.0 (gfx950)"
 
 namespace {
 
@@ -70,14 +90,14 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 // ---------------------------------------------------------------------------
-// per-precision scalar operations of the Chambolle update
+// scalar operations of the Chambolle update
 
-template <typename R> struct Arith;
+template <typename M> struct Arith;
 
 template <> struct Arith<float> {
     static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-    // p / d as p * (1/d): one reciprocal shared by both components
+    // one reciprocal shared by both components
     static __device__ __forceinline__ float inv_(float d) { return __builtin_amdgcn_rcpf(d); }
 };
 
@@ -87,16 +107,38 @@ template <> struct Arith<double> {
     static __device__ __forceinline__ double inv_(double d) { return 1.0 / d; }
 };
 
-// One Chambolle update of a pixel's dual vector (px, py) from the gradient
-// (ax, ay) of w = div p - g/dt:  p <- (p + tau a) / (1 + tau |a|).
-template <typename R>
-__device__ __forceinline__ void chambolle_update(R &px, R &py, R ax, R ay, R tau)
+// One Chambolle update of a pixel's dual vector from the gradient a of
+// div p - g/dt:  p <- (p + tau a) / (1 + tau |a|).
+// |a| is formed as ax*ax + ay*ay (not a fused multiply-add) so that the
+// update is symmetric in x and y, like the method.
+template <typename S, typename M>
+__device__ __forceinline__ void chambolle_update(S &px, S &py, S ax, S ay, S tau)
 {
-    using A = Arith<R>;
-    R nrm = A::sqrt_(A::fma_(ax, ax, ay * ay));
-    R r = A::inv_(A::fma_(tau, nrm, R(1)));
-    px = A::fma_(tau, ax, px) * r;
-    py = A::fma_(tau, ay, py) * r;
+    if constexpr (std::is_same<S, M>::value) {
+        using A = Arith<S>;
+        const S nrm = A::sqrt_(ax * ax + ay * ay);
+        const S r = A::inv_(A::fma_(tau, nrm, S(1)));
+        px = A::fma_(tau, ax, px) * r;
+        py = A::fma_(tau, ay, py) * r;
+    } else {
+        // float64 update in increment form, p += tau (a - |a| p) / (1 + tau |a|),
+        // with |a| and the reciprocal from the float32 hardware estimates
+        // (v_rsq_f32, v_rcp_f32) refined by one Newton step in float64
+        // (relative error ~1e-14; the float64 square root and division
+        // sequences cost several times more).  A zero gradient gives
+        // |a| = 0 through the select (its estimate is infinite).
+        const S x = ax * ax + ay * ay;
+        const float xf = (float)x;
+        S y = (S)__builtin_amdgcn_rsqf(xf);
+        y = __builtin_fma(S(0.5) * y, __builtin_fma(-(x * y), y, S(1)), y);
+        const S nrm = xf > 0.0f ? x * y : S(0);
+        const S den = __builtin_fma(tau, nrm, S(1));
+        S r = (S)__builtin_amdgcn_rcpf((float)den);
+        r = __builtin_fma(r, __builtin_fma(-den, r, S(1)), r);
+        const S tr = tau * r;
+        px += tr * __builtin_fma(-nrm, px, ax);
+        py += tr * __builtin_fma(-nrm, py, ay);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -118,7 +160,9 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Block of 256 threads (4 waves).  Every thread returns the block sum.
+constexpr int kThreads = 256;
+
+// Block of 256 threads (4 waves).  Every thread returns the block result.
 __device__ __forceinline__ double block_sum256(double v, double *sh)
 {
     v = wave_sum(v);
@@ -141,90 +185,97 @@ __device__ __forceinline__ double block_max256(double v, double *sh)
     return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-constexpr int kThreads = 256;
-
 // ---------------------------------------------------------------------------
 // kernels
 
-// u = f, gl = f/dt, p = 0 (buffer A), bands = 0; counts non-finite inputs.
-template <typename R>
+// u = f, G = grad f / dt (data term of the first solve), p = 0 (buffer A),
+// bands = 0; counts non-finite inputs.
+template <typename S, typename M>
 __global__ __launch_bounds__(kThreads) void k_init(const float *__restrict__ f, double *__restrict__ u,
-                                                   R *__restrict__ gl, R *__restrict__ px, R *__restrict__ py,
-                                                   double *__restrict__ bands, size_t n_all, int nbands,
-                                                   double dt, unsigned int *__restrict__ nonfinite)
+                                                   M *__restrict__ gx, M *__restrict__ gy, S *__restrict__ px,
+                                                   S *__restrict__ py, double *__restrict__ bands, int H, int W,
+                                                   size_t n_all, int nbands, double dt,
+                                                   unsigned int *__restrict__ nonfinite)
 {
     __shared__ double sh[4];
     double bad = 0.0;
+    const size_t plane = (size_t)H * (size_t)W;
     const size_t stride = (size_t)gridDim.x * kThreads;
     for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n_all; q += stride) {
+        const int qq = (int)(q % plane);
+        const int i = qq / W;
+        const int j = qq - i * W;
         const float v = f[q];
         if (!isfinite(v))
             bad += 1.0;
         u[q] = (double)v;
-        gl[q] = (R)((double)v / dt);
-        px[q] = R(0);
-        py[q] = R(0);
-        for (int j = 0; j < nbands; ++j)
-            bands[(size_t)j * n_all + q] = 0.0;
+        gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
+        gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
+        px[q] = S(0);
+        py[q] = S(0);
+        for (int k = 0; k < nbands; ++k)
+            bands[(size_t)k * n_all + q] = 0.0;
     }
     bad = block_sum256(bad, sh);
     if (threadIdx.x == 0 && bad > 0.0)
         atomicAdd(nonfinite, (unsigned int)bad);
 }
 
-__global__ __launch_bounds__(kThreads) void k_zero2(float *__restrict__ a, float *__restrict__ b, size_t n)
-{
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += stride) {
-        a[q] = 0.f;
-        b[q] = 0.f;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_zero2d(double *__restrict__ a, double *__restrict__ b, size_t n)
-{
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += stride) {
-        a[q] = 0.0;
-        b[q] = 0.0;
-    }
-}
-
 // Temporally blocked Chambolle iterations.
 //
-// Grid: (number of BX x BY output tiles, C).  The workgroup stages the
-// (BX+2TB) x (BY+2TB) region around its tile: the dual field (px, py) and
-// g/dt of every region pixel live in registers of the thread that owns the
-// pixel for all `iters` iterations; LDS only carries the values a neighbour
-// needs (px of the left pixel and py of the upper one for w, w of the right
-// and lower pixels for grad w).  One iteration on every region pixel:
-//     w   = ((px - px_left) + (py - py_up)) - g/dt        (div p - g/dt)
-//     a   = (w_right - w, w_down - w), zero on the last column / row
+// Chambolle's step needs a = grad(div p - g/dt).  It is evaluated as
+//     a = grad(div p) - G,   G = grad(g)/dt,
+// with G formed in float64 from the float64 flow state and stored in type M.
+// This is the same quantity; the order matters in float32: g/dt is large
+// (|g| <= 1, dt ~ 1e-3) and differencing two rounded values of it would bury
+// the small gradients of flat regions, whereas G carries only the relative
+// rounding of the gradient itself.
+//
+// Grid: (number of BX x BY output tiles, C); 1024 threads, so that every
+// SIMD of the CU has four waves to interleave (the per-pixel chain of LDS
+// reads, square root and reciprocal is long and a tile holds few pixels).
+// The workgroup stages the (BX+2TB) x (BY+2TB) region around its tile: the
+// dual field and G of every region pixel live in registers of the thread
+// that owns the pixel for all `iters` iterations; LDS only carries the
+// values a neighbour needs (px of the left pixel and py of the upper one for
+// div p, div p of the right and lower pixels for its gradient).  The LDS
+// planes carry a one-pixel ring that is never written, so neighbour reads
+// need no tests.  One iteration on every region pixel:
+//     d   = (px - px_left) + (py - py_up)                      (div p)
+//     a   = ((d_right - d) - Gx, (d_down - d) - Gy), zero on the last
+//           column / row and outside the image
 //     p  <- (p + tau a) / (1 + tau |a|)
-// Pixels outside the image hold p = 0 and are never updated, which realises
-// the Neumann divergence (p_x = 0 on the last column and p_y = 0 on the last
-// row is preserved by the update because a_x, a_y vanish there).  A region
-// pixel at distance d from the region edge is exact for d >= iteration count,
-// so after iters <= TB iterations the BX x BY centre is exact and is written.
-template <typename R, int BX, int BY, int TB>
-__global__ __launch_bounds__(kThreads) void k_chambolle_tile(
-    const R *__restrict__ pxi, const R *__restrict__ pyi, const R *__restrict__ gl, R *__restrict__ pxo,
-    R *__restrict__ pyo, int H, int W, int ntx, int ntiles, R tau, int iters)
+// Pixels outside the image start with p = 0 and a = 0, so they keep p = 0;
+// that realises the Neumann divergence (p_x = 0 on the last column and
+// p_y = 0 on the last row is preserved by the update because a_x, a_y vanish
+// there).  With zero_in set (first launch of a cold-started solve) the
+// incoming dual field is taken as zero instead of being read.  A region
+// pixel at distance e from the region edge is exact while the iteration
+// count is <= e, so after iters <= TB iterations the BX x BY centre is exact
+// and is written.
+constexpr int kTileThreads = 1024;
+
+template <typename S, typename M, int BX, int BY, int TB>
+__global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(
+    const S *__restrict__ pxi, const S *__restrict__ pyi, const M *__restrict__ gxi, const M *__restrict__ gyi,
+    S *__restrict__ pxo, S *__restrict__ pyo, int H, int W, int ntx, int ntiles, S tau, int iters, int zero_in)
 {
     constexpr int RX = BX + 2 * TB;
     constexpr int RY = BY + 2 * TB;
     constexpr int RN = RX * RY;
-    constexpr int PPT = (RN + kThreads - 1) / kThreads;
-    static_assert(PPT <= 32, "pixel masks are 32-bit");
-    __shared__ R s_px[RN];
-    __shared__ R s_py[RN];
-    __shared__ R s_w[RN];
+    constexpr int LX = RX + 2;            // LDS row pitch: region + zero ring
+    constexpr int LN = LX * (RY + 2);
+    constexpr int PPT = (RN + kTileThreads - 1) / kTileThreads;
+    __shared__ S s_px[LN];
+    __shared__ S s_py[LN];
+    __shared__ S s_d[LN];
 
     const size_t plane = (size_t)H * (size_t)W;
     const size_t coff = (size_t)blockIdx.y * plane;
     pxi += coff;
     pyi += coff;
-    gl += coff;
+    gxi += coff;
+    gyi += coff;
     pxo += coff;
     pyo += coff;
 
@@ -237,65 +288,85 @@ __global__ __launch_bounds__(kThreads) void k_chambolle_tile(
     const int oy = ty * BY - TB;
     const int ox = tx * BX - TB;
 
-    R px[PPT], py[PPT], g[PPT], w[PPT];
-    unsigned live = 0, xin = 0, yin = 0, outm = 0, hasl = 0, hasu = 0, hasr = 0, hasd = 0;
+    // zero ring (read by the outermost region pixels only)
+    for (int e = threadIdx.x; e < 2 * LX + 2 * RY; e += kTileThreads) {
+        int li;
+        if (e < LX)
+            li = e;                              // top row
+        else if (e < 2 * LX)
+            li = (RY + 1) * LX + (e - LX);       // bottom row
+        else if (e < 2 * LX + RY)
+            li = (e - 2 * LX + 1) * LX;          // left column
+        else
+            li = (e - 2 * LX - RY + 1) * LX + LX - 1; // right column
+        s_px[li] = S(0);
+        s_py[li] = S(0);
+        s_d[li] = S(0);
+    }
+
+    S px[PPT], py[PPT], d[PPT];
+    M gx[PPT], gy[PPT];
+    int li[PPT];     // LDS index of the pixel
+    bool mx[PPT];    // a_x is live: pixel inside the image and not on its last column
+    bool my[PPT];    // a_y is live: pixel inside the image and not on its last row
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        const int idx = threadIdx.x + m * kThreads;
-        R vx = R(0), vy = R(0), vg = R(0);
+        const int idx = threadIdx.x + m * kTileThreads;
+        S vx = S(0), vy = S(0);
+        M vgx = M(0), vgy = M(0);
+        bool ax_live = false, ay_live = false;
+        int l = 0;
         if (idx < RN) {
             const int ri = idx / RX;
             const int rj = idx - ri * RX;
             const int gi = oy + ri;
             const int gj = ox + rj;
-            if (rj > 0) hasl |= 1u << m;
-            if (ri > 0) hasu |= 1u << m;
-            if (rj < RX - 1) hasr |= 1u << m;
-            if (ri < RY - 1) hasd |= 1u << m;
+            l = (ri + 1) * LX + (rj + 1);
             if (gi >= 0 && gi < H && gj >= 0 && gj < W) {
                 const size_t q = (size_t)gi * W + gj;
-                vx = pxi[q];
-                vy = pyi[q];
-                vg = gl[q];
-                live |= 1u << m;
-                if (gj < W - 1) xin |= 1u << m;
-                if (gi < H - 1) yin |= 1u << m;
-                if (ri >= TB && ri < TB + BY && rj >= TB && rj < TB + BX) outm |= 1u << m;
+                if (!zero_in) {
+                    vx = pxi[q];
+                    vy = pyi[q];
+                }
+                vgx = gxi[q];
+                vgy = gyi[q];
+                ax_live = gj < W - 1;
+                ay_live = gi < H - 1;
             }
-            s_px[idx] = vx;
-            s_py[idx] = vy;
+            s_px[l] = vx;
+            s_py[l] = vy;
         }
+        li[m] = l;
         px[m] = vx;
         py[m] = vy;
-        g[m] = vg;
-        w[m] = R(0);
+        gx[m] = vgx;
+        gy[m] = vgy;
+        d[m] = S(0);
+        mx[m] = ax_live;
+        my[m] = ay_live;
     }
     __syncthreads();
 
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
         for (int m = 0; m < PPT; ++m) {
-            const int idx = threadIdx.x + m * kThreads;
-            if (idx < RN) {
-                const R pxl = ((hasl >> m) & 1u) ? s_px[idx - 1] : R(0);
-                const R pyu = ((hasu >> m) & 1u) ? s_py[idx - RX] : R(0);
-                const R wv = ((px[m] - pxl) + (py[m] - pyu)) - g[m];
-                w[m] = wv;
-                s_w[idx] = wv;
+            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
+                const int l = li[m];
+                const S dv = (px[m] - s_px[l - 1]) + (py[m] - s_py[l - LX]);
+                d[m] = dv;
+                s_d[l] = dv;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < PPT; ++m) {
-            const int idx = threadIdx.x + m * kThreads;
-            if ((live >> m) & 1u) {
-                const R wr = ((hasr >> m) & 1u) ? s_w[idx + 1] : w[m];
-                const R wd = ((hasd >> m) & 1u) ? s_w[idx + RX] : w[m];
-                const R ax = ((xin >> m) & 1u) ? wr - w[m] : R(0);
-                const R ay = ((yin >> m) & 1u) ? wd - w[m] : R(0);
-                chambolle_update<R>(px[m], py[m], ax, ay, tau);
-                s_px[idx] = px[m];
-                s_py[idx] = py[m];
+            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
+                const int l = li[m];
+                const S ax = mx[m] ? (s_d[l + 1] - d[m]) - (S)gx[m] : S(0);
+                const S ay = my[m] ? (s_d[l + LX] - d[m]) - (S)gy[m] : S(0);
+                chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
+                s_px[l] = px[m];
+                s_py[l] = py[m];
             }
         }
         __syncthreads();
@@ -303,29 +374,48 @@ __global__ __launch_bounds__(kThreads) void k_chambolle_tile(
 
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        if ((outm >> m) & 1u) {
-            const int idx = threadIdx.x + m * kThreads;
+        const int idx = threadIdx.x + m * kTileThreads;
+        if (idx < RN) {
             const int ri = idx / RX;
             const int rj = idx - ri * RX;
-            const size_t q = (size_t)(oy + ri) * W + (ox + rj);
-            pxo[q] = px[m];
-            pyo[q] = py[m];
+            const int gi = oy + ri;
+            const int gj = ox + rj;
+            if (ri >= TB && ri < TB + BY && rj >= TB && rj < TB + BX && gi < H && gj < W) {
+                const size_t q = (size_t)gi * W + gj;
+                pxo[q] = px[m];
+                pyo[q] = py[m];
+            }
         }
     }
+}
+
+// div p at pixel q = (i, j) of one channel plane, in float64 from the stored
+// dual field (zero outside the image).
+template <typename S>
+__device__ __forceinline__ double div_p(const S *__restrict__ px, const S *__restrict__ py, int q, int i, int j,
+                                        int W)
+{
+    const double pxl = (j > 0) ? (double)px[q - 1] : 0.0;
+    const double pyu = (i > 0) ? (double)py[q - W] : 0.0;
+    return ((double)px[q] - pxl) + ((double)py[q] - pyu);
 }
 
 // Outer step s of the flow, fused with the spectral transform.
 // Grid: (nblk, C), nblk fixed per image size so partial sums are reproducible.
 //   D_s     = dt div p                     (u_s - u_{s+1})
-//   u_{s+1} = u_s - D_s
+//   u_{s+1} = u_s - D_s                    (written to the other u buffer)
 //   s >= 1: phi_s dt = s (D_{s-1} - D_s)   added to the band holding s
 //           spart  <- block sum of |D_{s-1} - D_s|   (S(t_s) = s/dt * total)
 //   s == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t)
-//   gl      = u_{s+1} / dt                  (data term of the next solve)
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_flow_step(const R *__restrict__ px, const R *__restrict__ py,
-                                                        double *__restrict__ u, double *__restrict__ dprev,
-                                                        R *__restrict__ gl, double *__restrict__ band,
+//   G       = grad(u_{s+1}) / dt           (data term of the next solve; the
+//             right and lower neighbours' u_{s+1} are recomputed here with
+//             the same operations their own threads use, so they match bit
+//             for bit)
+template <typename S, typename M>
+__global__ __launch_bounds__(kThreads) void k_flow_step(const S *__restrict__ px, const S *__restrict__ py,
+                                                        const double *__restrict__ uin, double *__restrict__ uout,
+                                                        double *__restrict__ dprev, M *__restrict__ gx,
+                                                        M *__restrict__ gy, double *__restrict__ band,
                                                         double *__restrict__ resid, double *__restrict__ spart,
                                                         int H, int W, int C, int k, int K, double dt)
 {
@@ -335,21 +425,18 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const R *__restrict__ px
     const size_t coff = (size_t)c * (size_t)plane;
     px += coff;
     py += coff;
-    u += coff;
+    uin += coff;
+    uout += coff;
     dprev += coff;
-    gl += coff;
+    gx += coff;
+    gy += coff;
     const double kd = (double)k;
     double acc = 0.0;
     for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
         const int i = q / W;
         const int j = q - i * W;
-        const double pxc = (double)px[q];
-        const double pyc = (double)py[q];
-        const double pxl = (j > 0) ? (double)px[q - 1] : 0.0;
-        const double pyu = (i > 0) ? (double)py[q - W] : 0.0;
-        const double divp = (pxc - pxl) + (pyc - pyu);
-        const double D = dt * divp;
-        const double uo = u[q];
+        const double D = dt * div_p(px, py, q, i, j, W);
+        const double uo = uin[q];
         const double un = uo - D;
         if (k >= 1) {
             const double dl = dprev[q] - D;
@@ -358,9 +445,20 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const R *__restrict__ px
         }
         if (k == K)
             resid[coff + q] = uo + (double)K * D;
-        u[q] = un;
+        uout[q] = un;
         dprev[q] = D;
-        gl[q] = (R)(un / dt);
+        if (j < W - 1) {
+            const double unr = uin[q + 1] - dt * div_p(px, py, q + 1, i, j + 1, W);
+            gx[q] = (M)((unr - un) / dt);
+        } else {
+            gx[q] = M(0);
+        }
+        if (i < H - 1) {
+            const double und = uin[q + W] - dt * div_p(px, py, q + W, i + 1, j, W);
+            gy[q] = (M)((und - un) / dt);
+        } else {
+            gy[q] = M(0);
+        }
     }
     if (k >= 1) {
         acc = block_sum256(acc, sh);
@@ -400,39 +498,47 @@ __global__ __launch_bounds__(kThreads) void k_check(const float *__restrict__ f,
     }
 }
 
-// One block: S[c][k-1] = k/dt * sum of the step partials; the report.
-__global__ __launch_bounds__(kThreads) void k_reduce(const double *__restrict__ spart, const double *__restrict__ rpart,
-                                                     int C, int K, int nblk_step, int nblk_chk, int plane, double dt,
-                                                     double *__restrict__ S, double *__restrict__ stats,
-                                                     unsigned int *__restrict__ nonfinite)
+// S[c][k-1] = k/dt * (sum of the step partials of sample k, channel c):
+// one block per (k, c), each thread summing a fixed stride of partials,
+// then the block sum in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_reduce_s(const double *__restrict__ spart, int C, int K, int nblk,
+                                                       double dt, double *__restrict__ S)
 {
-    for (int t = threadIdx.x; t < C * K; t += kThreads) {
-        const int c = t / K;
-        const int k = t - c * K + 1;
-        const double *p = spart + ((size_t)(k - 1) * C + c) * nblk_step;
-        double s = 0.0;
-        for (int b = 0; b < nblk_step; ++b)
-            s += p[b];
-        S[t] = s * ((double)k / dt);
-    }
-    if (threadIdx.x == 0) {
-        double emax = 0.0, drift = 0.0;
-        for (int c = 0; c < C; ++c) {
-            double su = 0.0, sf = 0.0;
-            for (int b = 0; b < nblk_chk; ++b) {
-                const double *o = rpart + ((size_t)c * nblk_chk + b) * 3;
-                emax = fmax(emax, o[0]);
-                su += o[1];
-                sf += o[2];
-            }
-            drift = fmax(drift, fabs(su / (double)plane - sf / (double)plane));
+    __shared__ double sh[4];
+    const int t = blockIdx.x;            // (k-1) * C + c
+    const int k = t / C + 1;
+    const int c = t - (k - 1) * C;
+    const double *p = spart + (size_t)t * nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+        s += p[b];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0)
+        S[(size_t)c * K + (k - 1)] = s * ((double)k / dt);
+}
+
+// One thread: the report from the check partials.
+__global__ void k_report(const double *__restrict__ rpart, int C, int nblk_chk, int plane,
+                         double *__restrict__ stats, unsigned int *__restrict__ nonfinite)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double emax = 0.0, drift = 0.0;
+    for (int c = 0; c < C; ++c) {
+        double su = 0.0, sf = 0.0;
+        for (int b = 0; b < nblk_chk; ++b) {
+            const double *o = rpart + ((size_t)c * nblk_chk + b) * 3;
+            emax = fmax(emax, o[0]);
+            su += o[1];
+            sf += o[2];
         }
-        stats[0] = emax;
-        stats[1] = drift;
-        stats[2] = (double)(*nonfinite);
-        stats[3] = 0.0;
-        *nonfinite = 0u;
+        drift = fmax(drift, fabs(su / (double)plane - sf / (double)plane));
     }
+    stats[0] = emax;
+    stats[1] = drift;
+    stats[2] = (double)(*nonfinite);
+    stats[3] = 0.0;
+    *nonfinite = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -453,47 +559,37 @@ int blocks_for(size_t n, int cap)
 // size so that partial sums (and hence S) are reproducible.
 int plane_blocks(int plane) { return blocks_for((size_t)plane, 1024); }
 
-template <typename R>
-using TileKernel = void (*)(const R *, const R *, const R *, R *, R *, int, int, int, int, R, int);
+template <typename S, typename M>
+using TileKernel = void (*)(const S *, const S *, const M *, const M *, S *, S *, int, int, int, int, S, int, int);
 
-template <typename R> int max_tb();
-template <> int max_tb<float>() { return 16; }
-template <> int max_tb<double>() { return 8; }
+// Largest temporal blocking factor compiled for a mode (LDS and registers of
+// the (32+2TB)^2 region, which are sized by the dual-field type S).
+template <typename S> constexpr int max_tb() { return std::is_same<S, float>::value ? 16 : 8; }
 
 // Smallest compiled halo width >= t.
-template <typename R> TileKernel<R> tile_kernel(int t, int *tb);
-
-template <> TileKernel<float> tile_kernel<float>(int t, int *tb)
+template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
-    if (t <= 1) { *tb = 1; return k_chambolle_tile<float, kTileX, kTileY, 1>; }
-    if (t <= 2) { *tb = 2; return k_chambolle_tile<float, kTileX, kTileY, 2>; }
-    if (t <= 4) { *tb = 4; return k_chambolle_tile<float, kTileX, kTileY, 4>; }
-    if (t <= 8) { *tb = 8; return k_chambolle_tile<float, kTileX, kTileY, 8>; }
-    *tb = 16;
-    return k_chambolle_tile<float, kTileX, kTileY, 16>;
-}
-
-template <> TileKernel<double> tile_kernel<double>(int t, int *tb)
-{
-    if (t <= 1) { *tb = 1; return k_chambolle_tile<double, kTileX, kTileY, 1>; }
-    if (t <= 2) { *tb = 2; return k_chambolle_tile<double, kTileX, kTileY, 2>; }
-    if (t <= 4) { *tb = 4; return k_chambolle_tile<double, kTileX, kTileY, 4>; }
+    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1>; }
+    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2>; }
+    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4>; }
+    if constexpr (max_tb<S>() >= 16) {
+        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16>; }
+    }
     *tb = 8;
-    return k_chambolle_tile<double, kTileX, kTileY, 8>;
+    return k_chambolle_tile<S, M, kTileX, kTileY, 8>;
 }
 
 // ---------------------------------------------------------------------------
-// device scratch, cached per (device, precision) and grown on demand
+// device scratch, cached per (device, precision mode) and grown on demand
 
 struct Scratch {
-    size_t n_all = 0;      // C*H*W the plane buffers hold
-    size_t spart_n = 0;    // doubles in spart
-    size_t rpart_n = 0;    // doubles in rpart
-    size_t elem = 0;       // sizeof(R)
-    void *pa[2] = {nullptr, nullptr}; // dual field buffer A: px, py
-    void *pb[2] = {nullptr, nullptr}; // dual field buffer B: px, py
-    void *gl = nullptr;
-    double *u = nullptr;
+    size_t n_all = 0;                  // C*H*W the plane buffers hold
+    size_t spart_n = 0;                // doubles in spart
+    size_t rpart_n = 0;                // doubles in rpart
+    void *pa[2] = {nullptr, nullptr};  // dual field buffer A: px, py (type S)
+    void *pb[2] = {nullptr, nullptr};  // dual field buffer B: px, py (type S)
+    void *g[2] = {nullptr, nullptr};   // G = grad(g)/dt: x and y planes (type M)
+    double *u[2] = {nullptr, nullptr}; // flow state, double-buffered per step
     double *dprev = nullptr;
     double *spart = nullptr;
     double *rpart = nullptr;
@@ -508,8 +604,9 @@ struct HostStage {
 };
 
 constexpr int kMaxDevices = 64;
+constexpr int kModes = 3;
 std::mutex g_mu;
-Scratch g_scratch[kMaxDevices][2];
+Scratch g_scratch[kMaxDevices][kModes];
 HostStage g_stage[kMaxDevices];
 
 // Benchmark timing of the Chambolle kernel: event pairs around each launch.
@@ -562,47 +659,51 @@ void free_ptr(void *&p)
     p = nullptr;
 }
 
+template <typename T> void free_typed(T *&p)
+{
+    void *v = p;
+    free_ptr(v);
+    p = nullptr;
+}
+
 void free_scratch(Scratch &s)
 {
-    free_ptr(s.pa[0]);
-    free_ptr(s.pa[1]);
-    free_ptr(s.pb[0]);
-    free_ptr(s.pb[1]);
-    free_ptr(s.gl);
-    void *p;
-    p = s.u; free_ptr(p); s.u = nullptr;
-    p = s.dprev; free_ptr(p); s.dprev = nullptr;
-    p = s.spart; free_ptr(p); s.spart = nullptr;
-    p = s.rpart; free_ptr(p); s.rpart = nullptr;
-    p = s.nonfinite; free_ptr(p); s.nonfinite = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        free_ptr(s.pa[i]);
+        free_ptr(s.pb[i]);
+        free_ptr(s.g[i]);
+        free_typed(s.u[i]);
+    }
+    free_typed(s.dprev);
+    free_typed(s.spart);
+    free_typed(s.rpart);
+    free_typed(s.nonfinite);
     s.n_all = s.spart_n = s.rpart_n = 0;
 }
 
 void free_stage(HostStage &h)
 {
-    void *p;
-    p = h.f; free_ptr(p); h.f = nullptr;
-    p = h.bands; free_ptr(p); h.bands = nullptr;
-    p = h.S; free_ptr(p); h.S = nullptr;
-    p = h.res; free_ptr(p); h.res = nullptr;
-    p = h.stats; free_ptr(p); h.stats = nullptr;
+    free_typed(h.f);
+    free_typed(h.bands);
+    free_typed(h.S);
+    free_typed(h.res);
+    free_typed(h.stats);
     h.f_n = h.bands_n = h.s_n = h.r_n = 0;
 }
 
-int ensure_scratch(Scratch &s, size_t elem, size_t n_all, size_t spart_n, size_t rpart_n)
+int ensure_scratch(Scratch &s, size_t elem_s, size_t elem_m, size_t n_all, size_t spart_n, size_t rpart_n)
 {
-    if (s.elem == elem && s.n_all >= n_all && s.spart_n >= spart_n && s.rpart_n >= rpart_n && s.u)
+    if (s.n_all >= n_all && s.spart_n >= spart_n && s.rpart_n >= rpart_n && s.u[0])
         return TVSPEC_OK;
     // buffers may still be in use by earlier enqueued work
     HIP_TRY(hipDeviceSynchronize());
     free_scratch(s);
-    s.elem = elem;
     for (int i = 0; i < 2; ++i) {
-        HIP_TRY(hipMalloc(&s.pa[i], n_all * elem));
-        HIP_TRY(hipMalloc(&s.pb[i], n_all * elem));
+        HIP_TRY(hipMalloc(&s.pa[i], n_all * elem_s));
+        HIP_TRY(hipMalloc(&s.pb[i], n_all * elem_s));
+        HIP_TRY(hipMalloc(&s.g[i], n_all * elem_m));
+        HIP_TRY(hipMalloc((void **)&s.u[i], n_all * sizeof(double)));
     }
-    HIP_TRY(hipMalloc(&s.gl, n_all * elem));
-    HIP_TRY(hipMalloc((void **)&s.u, n_all * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s.dprev, n_all * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s.spart, spart_n * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s.rpart, rpart_n * sizeof(double)));
@@ -653,9 +754,10 @@ int validate_opts(double tau, int warm, int precision, int ipl)
         return fail(TVSPEC_EINVAL, "tau must be in (0, 0.25]");
     if (warm != 0 && warm != 1)
         return fail(TVSPEC_EINVAL, "warm_start must be 0 or 1");
-    if (precision != TVSPEC_PRECISION_F32 && precision != TVSPEC_PRECISION_F64)
-        return fail(TVSPEC_EINVAL, "precision must be TVSPEC_PRECISION_F32 or _F64");
-    const int maxt = precision == TVSPEC_PRECISION_F32 ? 16 : 8;
+    if (precision != TVSPEC_PRECISION_F32 && precision != TVSPEC_PRECISION_F64 &&
+        precision != TVSPEC_PRECISION_MIXED)
+        return fail(TVSPEC_EINVAL, "precision must be TVSPEC_PRECISION_F32, _F64 or _MIXED");
+    const int maxt = precision == TVSPEC_PRECISION_F32 ? max_tb<float>() : max_tb<double>();
     if (ipl < 0 || ipl > maxt)
         return fail(TVSPEC_EINVAL, "iters_per_launch out of range");
     return TVSPEC_OK;
@@ -664,9 +766,9 @@ int validate_opts(double tau, int warm, int precision, int ipl)
 // ---------------------------------------------------------------------------
 // the decomposition, enqueued on a stream
 
-template <typename R>
+template <typename S, typename M>
 int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, const int *edges, int nb,
-            double *bands, double *S, double *res, double *stats, double tau, int warm, int ipl,
+            double *bands, double *Sout, double *res, double *stats, double tau, int warm, int ipl,
             hipStream_t st, Scratch &sc)
 {
     const int plane = H * W;
@@ -674,16 +776,17 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
     const int nblk = plane_blocks(plane);
     const size_t spart_n = (size_t)K * C * nblk;
     const size_t rpart_n = (size_t)C * nblk * 3;
-    int rc = ensure_scratch(sc, sizeof(R), n_all, spart_n, rpart_n);
+    int rc = ensure_scratch(sc, sizeof(S), sizeof(M), n_all, spart_n, rpart_n);
     if (rc != TVSPEC_OK)
         return rc;
 
-    R *pbuf[2][2] = {{(R *)sc.pa[0], (R *)sc.pa[1]}, {(R *)sc.pb[0], (R *)sc.pb[1]}};
-    R *gl = (R *)sc.gl;
+    S *pbuf[2][2] = {{(S *)sc.pa[0], (S *)sc.pa[1]}, {(S *)sc.pb[0], (S *)sc.pb[1]}};
+    M *gx = (M *)sc.g[0];
+    M *gy = (M *)sc.g[1];
 
     int tb = 0;
     const int want = ipl > 0 ? ipl : 8;
-    TileKernel<R> kt = tile_kernel<R>(want < max_tb<R>() ? want : max_tb<R>(), &tb);
+    TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
     const int ntx = (W + kTileX - 1) / kTileX;
     const int nty = (H + kTileY - 1) / kTileY;
     const int ntiles = ntx * nty;
@@ -696,21 +799,16 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
             band_of[k] = j;
 
     const int gblk = blocks_for(n_all, 4096);
-    hipLaunchKernelGGL(k_init<R>, dim3(gblk), dim3(kThreads), 0, st, f, sc.u, gl, pbuf[0][0], pbuf[0][1], bands,
-                       n_all, nb, dt, sc.nonfinite);
+    hipLaunchKernelGGL((k_init<S, M>), dim3(gblk), dim3(kThreads), 0, st, f, sc.u[0], gx, gy, pbuf[0][0],
+                       pbuf[0][1], bands, H, W, n_all, nb, dt, sc.nonfinite);
     HIP_TRY(hipGetLastError());
 
-    int cur = 0;
+    int cur = 0;  // dual field buffer holding the current iterate
+    int ucur = 0; // u buffer holding u_s
     for (int s = 0; s <= K; ++s) {
-        if (!warm && s > 0) {
-            if (sizeof(R) == 4)
-                hipLaunchKernelGGL(k_zero2, dim3(gblk), dim3(kThreads), 0, st, (float *)pbuf[cur][0],
-                                   (float *)pbuf[cur][1], n_all);
-            else
-                hipLaunchKernelGGL(k_zero2d, dim3(gblk), dim3(kThreads), 0, st, (double *)pbuf[cur][0],
-                                   (double *)pbuf[cur][1], n_all);
-        }
         for (int done = 0; done < iters;) {
+            // cold start: the first launch of a solve starts from p = 0
+            const int zero_in = (!warm && done == 0) ? 1 : 0;
             const int it = (iters - done) < per_launch ? (iters - done) : per_launch;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (g_timing.on) {
@@ -718,8 +816,8 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
                     return rc;
                 HIP_TRY(hipEventRecord(e0, st));
             }
-            hipLaunchKernelGGL(kt, dim3(ntiles, C), dim3(kThreads), 0, st, pbuf[cur][0], pbuf[cur][1], gl,
-                               pbuf[1 - cur][0], pbuf[1 - cur][1], H, W, ntx, ntiles, (R)tau, it);
+            hipLaunchKernelGGL(kt, dim3(ntiles, C), dim3(kTileThreads), 0, st, pbuf[cur][0], pbuf[cur][1], gx, gy,
+                               pbuf[1 - cur][0], pbuf[1 - cur][1], H, W, ntx, ntiles, (S)tau, it, zero_in);
             if (g_timing.on) {
                 HIP_TRY(hipEventRecord(e1, st));
                 ++g_timing.launches;
@@ -729,13 +827,15 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
             done += it;
         }
         double *band = s >= 1 ? bands + (size_t)band_of[s] * n_all : nullptr;
-        hipLaunchKernelGGL(k_flow_step<R>, dim3(nblk, C), dim3(kThreads), 0, st, pbuf[cur][0], pbuf[cur][1],
-                           sc.u, sc.dprev, gl, band, res, sc.spart, H, W, C, s, K, dt);
+        hipLaunchKernelGGL((k_flow_step<S, M>), dim3(nblk, C), dim3(kThreads), 0, st, pbuf[cur][0], pbuf[cur][1],
+                           sc.u[ucur], sc.u[1 - ucur], sc.dprev, gx, gy, band, res, sc.spart, H, W, C, s, K, dt);
+        ucur = 1 - ucur;
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_check, dim3(nblk, C), dim3(kThreads), 0, st, f, bands, res, sc.u, plane, C, nb, sc.rpart);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, sc.spart, sc.rpart, C, K, nblk, nblk, plane, dt, S,
-                       stats, sc.nonfinite);
+    hipLaunchKernelGGL(k_check, dim3(nblk, C), dim3(kThreads), 0, st, f, bands, res, sc.u[ucur], plane, C, nb,
+                       sc.rpart);
+    hipLaunchKernelGGL(k_reduce_s, dim3(K * C), dim3(kThreads), 0, st, sc.spart, C, K, nblk, dt, Sout);
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, st, sc.rpart, C, nblk, plane, stats, sc.nonfinite);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -748,20 +848,25 @@ int decompose_on_device(const float *f, int H, int W, int C, double dt, int K, i
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= kMaxDevices)
         return fail(TVSPEC_EDEVICE, "device index out of range");
-    if (precision == TVSPEC_PRECISION_F32)
-        return enqueue<float>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
-                              g_scratch[dev][0]);
-    return enqueue<double>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
-                           g_scratch[dev][1]);
+    Scratch &sc = g_scratch[dev][precision];
+    switch (precision) {
+    case TVSPEC_PRECISION_F32:
+        return enqueue<float, float>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
+                                     sc);
+    case TVSPEC_PRECISION_F64:
+        return enqueue<double, double>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
+                                       sc);
+    default:
+        return enqueue<double, float>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
+                                      sc);
+    }
 }
 
 template <typename T> int grow(T *&p, size_t &cap, size_t n)
 {
     if (cap >= n && p)
         return TVSPEC_OK;
-    void *v = p;
-    free_ptr(v);
-    p = nullptr;
+    free_typed(p);
     cap = 0;
     HIP_TRY(hipMalloc((void **)&p, n * sizeof(T)));
     cap = n;
@@ -823,7 +928,7 @@ extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
 
     HIP_TRY(hipMemcpyAsync(h.f, f, n_all * sizeof(float), hipMemcpyHostToDevice, h.stream));
     rc = decompose_on_device(h.f, H, W, C, dt, K, inner_iters, band_edges, n_bands, h.bands, h.S, h.res, h.stats,
-                             TVSPEC_DEFAULT_TAU, 1, TVSPEC_PRECISION_F32, 0, h.stream);
+                             TVSPEC_DEFAULT_TAU, 1, TVSPEC_DEFAULT_PRECISION, 0, h.stream);
     if (rc != TVSPEC_OK)
         return rc;
     HIP_TRY(hipMemcpyAsync(bands, h.bands, nb_n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
@@ -889,14 +994,16 @@ extern "C" void tvspec_release(void)
     if (hipGetDeviceCount(&ndev) != hipSuccess)
         return;
     for (int d = 0; d < ndev && d < kMaxDevices; ++d) {
-        bool any = g_stage[d].stream || g_scratch[d][0].u || g_scratch[d][1].u || g_stage[d].f;
+        bool any = g_stage[d].stream || g_stage[d].f;
+        for (int m = 0; m < kModes; ++m)
+            any = any || g_scratch[d][m].u[0];
         if (!any)
             continue;
         if (hipSetDevice(d) != hipSuccess)
             continue;
         (void)hipDeviceSynchronize();
-        free_scratch(g_scratch[d][0]);
-        free_scratch(g_scratch[d][1]);
+        for (int m = 0; m < kModes; ++m)
+            free_scratch(g_scratch[d][m]);
         free_stage(g_stage[d]);
         if (g_stage[d].stream) {
             (void)hipStreamDestroy(g_stage[d].stream);

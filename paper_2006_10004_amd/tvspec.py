@@ -26,6 +26,9 @@ TVSPEC_ENOMEM = -3
 TVSPEC_EDEVICE = -4
 TVSPEC_PRECISION_F32 = 0
 TVSPEC_PRECISION_F64 = 1
+TVSPEC_PRECISION_MIXED = 2
+PRECISIONS = {"f32": TVSPEC_PRECISION_F32, "f64": TVSPEC_PRECISION_F64, "mixed": TVSPEC_PRECISION_MIXED}
+DEFAULT_PRECISION = "mixed"
 TVSPEC_DEFAULT_TAU = 0.248
 TVSPEC_NSTATS = 4
 
@@ -141,8 +144,8 @@ def tvspec_decompose(f: np.ndarray, dt: float, K: int, inner_iters: int, band_ed
 
 
 def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges,
-                         tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = True,
-                         precision: str = "f32", iters_per_launch: int = 0,
+                         tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = False,
+                         precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
                          stream: torch.cuda.Stream | None = None, out: dict | None = None):
     """Device entry point: f is a (C,H,W) or (H,W) float32 tensor on a GPU.
 
@@ -162,7 +165,7 @@ def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, b
     C, H, W = f.shape
     e = _edges_array(band_edges)
     B = e.size - 1
-    prec = {"f32": TVSPEC_PRECISION_F32, "f64": TVSPEC_PRECISION_F64}[precision]
+    prec = PRECISIONS[precision]
     dev = f.device
     if out is None:
         out = {

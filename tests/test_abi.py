@@ -107,8 +107,8 @@ def test_device_entry_validation_options():
     e = np.array([0, 4], dtype=np.int32)
     fake = vp(0x1000)  # never dereferenced: validation fails first
     base = dict(tau=0.248, warm=1, prec=0, ipl=0)
-    for bad in (dict(tau=0.0), dict(tau=0.26), dict(warm=2), dict(prec=2), dict(ipl=-1), dict(ipl=17),
-                dict(prec=1, ipl=9)):
+    for bad in (dict(tau=0.0), dict(tau=0.26), dict(warm=2), dict(prec=3), dict(prec=-1), dict(ipl=-1),
+                dict(ipl=17), dict(prec=1, ipl=9), dict(prec=2, ipl=9)):
         a = dict(base)
         a.update(bad)
         rc = lib.tvspec_decompose_dev(fake, 8, 8, 1, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake, fake, fake,

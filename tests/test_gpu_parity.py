@@ -1,13 +1,17 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
-Tolerances (stated by the build's target and derived in the design notes):
-  bands, residual    max-abs 2e-4 for images in [0, 1], either precision;
-  S(t_k), float64    max_k |S_gpu - S_ref| / max_k S_ref <= 1e-6;
-  S(t_k), float32    the same ratio <= 5e-3: S sums |phi| over every pixel,
-                     so the float32 rounding floor of the inner iterate
-                     (eps32 * |g|/dt per evaluation of w) is summed over the
-                     whole image; measured ~1e-3 at 64x64;
-  recon / mean       float64 round-off (1e-12) -- the band increments use the
+Tolerances:
+  bands, residual    max-abs 2e-4 (images in [0, 1]) for the default MIXED
+                     and the F64 modes at every size tested, including the
+                     full 512x512 workload; the F32 mode meets it at 64x64
+                     (~1.5e-4) but not on the long 512x512 flow, where its
+                     rounding moves the bands by ~4.5e-4 (its test there is a
+                     regression guard at 1e-3, not a parity claim);
+  S(t_k)             max_k |S_gpu - S_ref| / max_k S_ref <= 1e-6 for MIXED and
+                     F64; <= 5e-3 for F32 (S sums |phi| over every pixel, so
+                     the float32 rounding floor of the iterate is summed over
+                     the whole image; measured ~7e-4 at 64x64);
+  recon / mean       float64 round-off (1e-12): the band increments use the
                      stored float64 flow, so the identity telescopes exactly.
 Bit-exact checks: launch configuration (temporal blocking factor), channels
 vs separate calls, negation, scaling by 2 with dt scaled by 2, transposition,
@@ -46,7 +50,7 @@ def s_rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def check_parity(g, r, s_tol, b_tol=TOL_BANDS):
+def check_parity(g, r, s_tol=TOL_S64, b_tol=TOL_BANDS):
     assert np.abs(g["bands"] - r["bands"]).max() <= b_tol
     assert np.abs(g["residual"] - r["residual"]).max() <= b_tol
     if np.abs(r["S"]).max() > 0:
@@ -57,10 +61,18 @@ def check_parity(g, r, s_tol, b_tol=TOL_BANDS):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_small64_parity_f32(tv, orc, seed):
+def test_small64_parity_default(tv, orc, seed):
     f = synth.shapes_image(synth.SMALL_64, seed)
     r = orc.decompose(f, **SMALL)
     g = gpu(tv, f, **SMALL)
+    check_parity(g, r, TOL_S64, b_tol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_small64_parity_f32(tv, orc, seed):
+    f = synth.shapes_image(synth.SMALL_64, seed)
+    r = orc.decompose(f, **SMALL)
+    g = gpu(tv, f, precision="f32", **SMALL)
     check_parity(g, r, TOL_S32)
 
 
@@ -73,7 +85,7 @@ def test_small64_parity_f64(tv, orc, seed):
 
 
 @pytest.mark.parametrize("H,W,C", [(2, 2, 1), (2, 45, 1), (45, 2, 1), (37, 53, 2), (100, 70, 3), (33, 97, 1)])
-@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("precision", ["f32", "f64", "mixed"])
 def test_ragged_shapes_parity(tv, orc, H, W, C, precision):
     """Shapes that are not tile multiples, span several tiles, and the 2-pixel
     degenerate widths."""
@@ -84,7 +96,8 @@ def test_ragged_shapes_parity(tv, orc, H, W, C, precision):
     check_parity(g, r, TOL_S32 if precision == "f32" else TOL_S64)
 
 
-@pytest.mark.parametrize("precision,ts", [("f32", [1, 2, 3, 5, 8, 13, 16]), ("f64", [1, 3, 8])])
+@pytest.mark.parametrize("precision,ts", [("f32", [1, 2, 3, 5, 8, 13, 16]), ("f64", [1, 3, 8]),
+                                          ("mixed", [1, 2, 5, 8])])
 def test_launch_configuration_does_not_change_results(tv, precision, ts):
     f = synth.shapes_image(synth.ShapeSpec(75, 101, 2, 8), seed=5)
     kw = dict(dt=0.01, K=7, iters=29, edges=[0, 1, 2, 4, 7], precision=precision)
@@ -124,15 +137,34 @@ def test_negation_scaling_transpose_exact(tv):
 
 def test_half_plane_closed_form(tv):
     """The half-plane eigenfunction on the GPU against its closed form (no
-    oracle): phi_8 dt = f - mean, S(t_8) = 48, residual = mean."""
+    oracle).  Warm start, extinction at 8 dt: phi_8 dt = f - mean,
+    S(t_8) = 48, residual = mean."""
     f = synth.step_image(3, 4, 6, 1.0)
     fm = f.astype(np.float64) - 0.4
-    for precision, tol in (("f64", 1e-12), ("f32", 5e-5)):
-        g = gpu(tv, f, 0.3, 10, 2000, [0, 1, 2, 4, 8, 10], precision=precision)
+    for precision, tol in (("f64", 1e-12), ("mixed", 1e-6), ("f32", 5e-5)):
+        g = gpu(tv, f, 0.3, 10, 2000, [0, 1, 2, 4, 8, 10], precision=precision, warm_start=True)
         assert np.abs(g["bands"][3, 0] - fm).max() < tol
         assert np.abs(np.delete(g["bands"], 3, axis=0)).max() < tol
         assert np.abs(g["residual"][0] - 0.4).max() < tol
         assert abs(g["S"][0, 7] - 48.0) < 48.0 * tol * 10
+
+
+def test_half_plane_two_samples_cold(tv):
+    """Cold start, extinction inside step 7 (T*/dt = 6.86): phi on samples 6
+    and 7 from the exact linear flow."""
+    f = synth.step_image(3, 4, 6, 1.0)
+    f64 = f.astype(np.float64)
+    dt, K, t_ext = 0.35, 10, 2.4
+    u = [0.4 + (f64 - 0.4) * max(0.0, 1.0 - k * dt / t_ext) for k in range(K + 2)]
+    phidt = [k * (u[k - 1] - 2 * u[k] + u[k + 1]) for k in range(1, K + 1)]
+    edges = [0, 1, 2, 4, 8, 10]
+    for precision, tol in (("f64", 1e-11), ("mixed", 1e-6), ("f32", 5e-5)):
+        g = gpu(tv, f, dt, K, 10000, edges, precision=precision)
+        for j in range(5):
+            want = sum(phidt[k - 1] for k in range(edges[j] + 1, edges[j + 1] + 1))
+            assert np.abs(g["bands"][j, 0] - want).max() < tol
+        S_want = np.array([np.abs(p).sum() / dt for p in phidt])
+        assert np.abs(g["S"][0] - S_want).max() <= tol * 10 * S_want.max()
 
 
 def test_constant_image_exact(tv):
@@ -149,7 +181,7 @@ def test_options_parity(tv, orc, warm, tau):
     kw = dict(dt=0.005, K=20, iters=50, edges=[0, 1, 2, 4, 20])
     r = orc.decompose(f, tau=tau, warm=warm, **kw)
     g = gpu(tv, f, tau=tau, warm_start=warm, **kw)
-    check_parity(g, r, TOL_S32)
+    check_parity(g, r)
 
 
 def test_minimal_sizes(tv, orc):
@@ -158,13 +190,13 @@ def test_minimal_sizes(tv, orc):
     for K, iters, edges in ((1, 1, [0, 1]), (3, 1, [0, 3]), (2, 5, [0, 1, 2])):
         r = orc.decompose(f, 0.05, K, iters, edges)
         g = gpu(tv, f, 0.05, K, iters, edges)
-        check_parity(g, r, TOL_S32)
+        check_parity(g, r)
 
 
 def test_host_entry_point_equals_device(tv):
     f = synth.shapes_image(synth.ShapeSpec(50, 60, 2, 6), seed=6)
     kw = dict(dt=0.01, K=6, iters=20)
-    h = tv.tvspec_decompose(f, band_edges=[0, 1, 2, 6], **kw)
+    h = tv.tvspec_decompose(f, kw["dt"], kw["K"], kw["iters"], [0, 1, 2, 6])
     g = gpu(tv, f, edges=[0, 1, 2, 6], **kw)
     for k in ("bands", "S", "residual"):
         assert np.array_equal(h[k], g[k])
@@ -226,11 +258,14 @@ def test_kernel_timing_counts(tv):
 
 @pytest.mark.slow
 def test_full_512_workload_parity(tv, orc):
-    """The 512x512 benchmark workload at full size and in the launch
-    configuration the benchmark times, against the full oracle run."""
+    """The 512x512 benchmark workload at full size (dt 0.002, K 200, 300
+    iterations, 8 dyadic bands) and in the launch configuration the
+    benchmark times, against the full oracle run: the default MIXED and the
+    F64 modes to the full tolerance, F32 to its documented envelope."""
     f = synth.shapes_image(synth.IMAGE_512, 0)
     edges = [0, 1, 2, 4, 8, 16, 32, 64, 200]
     kw = dict(dt=0.002, K=200, iters=300, edges=edges)
-    g = gpu(tv, f, **kw)
     r = orc.decompose(f, **kw)
-    check_parity(g, r, TOL_S32)
+    check_parity(gpu(tv, f, **kw), r)
+    check_parity(gpu(tv, f, precision="f64", **kw), r)
+    check_parity(gpu(tv, f, precision="f32", **kw), r, s_tol=TOL_S32, b_tol=1e-3)
