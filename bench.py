@@ -41,6 +41,28 @@ DTYPE = {"f32": "f32", "mixed": "f64 (f32-seeded sqrt/rcp)", "f64": "f64"}
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_chambolle_tile_512x512_mixed_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "tvspec.hip")
+
+
+def measured_traffic(precision, iters_per_launch):
+    """HBM bytes per tile-kernel launch from the committed counter record, or
+    None when the record is for another configuration or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    import re
+    if precision != "mixed" or iters_per_launch not in (0, 8) or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(TRAFFIC_RECORD).read(), flags=re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -74,6 +96,9 @@ def main():
     ap.add_argument("--latency-calls", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run 4 plain device copies of MIB MiB each "
+                         "(reference dispatches for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -83,8 +108,19 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                          "dispatches": 4}), flush=True)
+        return
+
     from paper_2006_10004_amd import synth, tvspec
 
     wl = dict(WORKLOAD)
@@ -172,13 +208,18 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.precision, args.iters_per_launch),
             "avg_launch_us": avg_ms * 1e3,
             "launches_per_step": t["launches"],
             "bytes_per_launch": per_launch_bytes,
             "kernel_share_of_step": t["kernel_ms"] / ms_per_step,
         }
         print("bench: roofline pass done", file=sys.stderr, flush=True)
+
+    # the host entry point (host buffers, PCIe-inclusive), once, for reference
+    t1 = time.perf_counter()
+    tvspec.tvspec_decompose(f_host, wl["dt"], wl["K"], wl["inner_iters"], edges)
+    rec["host_entry_ms"] = (time.perf_counter() - t1) * 1e3
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the same workload ...", file=sys.stderr, flush=True)

@@ -144,13 +144,13 @@ int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
 int tvspec_dyadic_edges(int K, int n_bands, int *edges);
 
 /*
- * Kernel timing for benchmarks.  While enabled (on = 1), every launch of the
- * Chambolle iteration kernel is bracketed by a pair of hipEvents recorded on
- * its launch stream.  tvspec_timing_read() waits for the recorded events,
- * returns the summed kernel time (ms), the number of launches and the number
- * of pixel-iterations (pixels x Chambolle iterations) they performed, and
- * clears the record.  Any pointer may be NULL.  Enabling adds a little host
- * work per launch; leave it off for throughput runs.
+ * Kernel timing for benchmarks.  While enabled (on = 1), the back-to-back
+ * launches of the Chambolle iteration kernel of every ROF solve are
+ * bracketed by one pair of hipEvents recorded on their stream.
+ * tvspec_timing_read() waits for the recorded events, returns the summed
+ * time (ms), the number of launches and the number of pixel-iterations
+ * (pixels x Chambolle iterations) they performed, and clears the record.
+ * Any pointer may be NULL.  Leave it off for throughput runs.
  * Errors: TVSPEC_EDEVICE (event creation, query or timing failed).
  */
 int tvspec_timing_enable(int on);

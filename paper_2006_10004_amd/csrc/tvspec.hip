@@ -125,13 +125,14 @@ __device__ __forceinline__ void chambolle_update(S &px, S &py, S ax, S ay, S tau
         // with |a| and the reciprocal from the float32 hardware estimates
         // (v_rsq_f32, v_rcp_f32) refined by one Newton step in float64
         // (relative error ~1e-14; the float64 square root and division
-        // sequences cost several times more).  A zero gradient gives
-        // |a| = 0 through the select (its estimate is infinite).
+        // sequences cost several times more).  Below |a| = 1e-15 the
+        // estimate's argument would leave the float32 normal range, and |a| is
+        // taken as 0: the increment then differs by at most tau |a| |p|, far
+        // below the rounding of p.
         const S x = ax * ax + ay * ay;
-        const float xf = (float)x;
-        S y = (S)__builtin_amdgcn_rsqf(xf);
+        S y = (S)__builtin_amdgcn_rsqf((float)x);
         y = __builtin_fma(S(0.5) * y, __builtin_fma(-(x * y), y, S(1)), y);
-        const S nrm = xf > 0.0f ? x * y : S(0);
+        const S nrm = x > S(1e-30) ? x * y : S(0);
         const S den = __builtin_fma(tau, nrm, S(1));
         S r = (S)__builtin_amdgcn_rcpf((float)den);
         r = __builtin_fma(r, __builtin_fma(-den, r, S(1)), r);
@@ -304,11 +305,10 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(
         s_d[li] = S(0);
     }
 
-    S px[PPT], py[PPT], d[PPT];
-    M gx[PPT], gy[PPT];
+    S px[PPT], py[PPT], d[PPT], gx[PPT], gy[PPT];
     int li[PPT];     // LDS index of the pixel
-    bool mx[PPT];    // a_x is live: pixel inside the image and not on its last column
-    bool my[PPT];    // a_y is live: pixel inside the image and not on its last row
+    S mx[PPT];       // 1 where a_x is live (inside the image, not its last column), else 0
+    S my[PPT];       // 1 where a_y is live (inside the image, not its last row), else 0
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int idx = threadIdx.x + m * kTileThreads;
@@ -339,11 +339,11 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(
         li[m] = l;
         px[m] = vx;
         py[m] = vy;
-        gx[m] = vgx;
-        gy[m] = vgy;
+        gx[m] = (S)vgx;
+        gy[m] = (S)vgy;
         d[m] = S(0);
-        mx[m] = ax_live;
-        my[m] = ay_live;
+        mx[m] = ax_live ? S(1) : S(0);
+        my[m] = ay_live ? S(1) : S(0);
     }
     __syncthreads();
 
@@ -362,8 +362,13 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(
         for (int m = 0; m < PPT; ++m) {
             if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
                 const int l = li[m];
-                const S ax = mx[m] ? (s_d[l + 1] - d[m]) - (S)gx[m] : S(0);
-                const S ay = my[m] ? (s_d[l + LX] - d[m]) - (S)gy[m] : S(0);
+                // unconditional LDS reads; the boundary masks multiply (a
+                // select around the reads compiles to branches that expose
+                // the LDS latency of every pixel)
+                const S dr = s_d[l + 1];
+                const S dd = s_d[l + LX];
+                const S ax = ((dr - d[m]) - gx[m]) * mx[m];
+                const S ay = ((dd - d[m]) - gy[m]) * my[m];
                 chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
                 s_px[l] = px[m];
                 s_py[l] = py[m];
@@ -517,28 +522,34 @@ __global__ __launch_bounds__(kThreads) void k_reduce_s(const double *__restrict_
         S[(size_t)c * K + (k - 1)] = s * ((double)k / dt);
 }
 
-// One thread: the report from the check partials.
-__global__ void k_report(const double *__restrict__ rpart, int C, int nblk_chk, int plane,
-                         double *__restrict__ stats, unsigned int *__restrict__ nonfinite)
+// One block: the report from the check partials (fixed reduction order).
+__global__ __launch_bounds__(kThreads) void k_report(const double *__restrict__ rpart, int C, int nblk_chk,
+                                                     int plane, double *__restrict__ stats,
+                                                     unsigned int *__restrict__ nonfinite)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
+    __shared__ double sh[4];
     double emax = 0.0, drift = 0.0;
     for (int c = 0; c < C; ++c) {
-        double su = 0.0, sf = 0.0;
-        for (int b = 0; b < nblk_chk; ++b) {
+        double e = 0.0, su = 0.0, sf = 0.0;
+        for (int b = threadIdx.x; b < nblk_chk; b += kThreads) {
             const double *o = rpart + ((size_t)c * nblk_chk + b) * 3;
-            emax = fmax(emax, o[0]);
+            e = fmax(e, o[0]);
             su += o[1];
             sf += o[2];
         }
+        e = block_max256(e, sh);
+        su = block_sum256(su, sh);
+        sf = block_sum256(sf, sh);
+        emax = fmax(emax, e);
         drift = fmax(drift, fabs(su / (double)plane - sf / (double)plane));
     }
-    stats[0] = emax;
-    stats[1] = drift;
-    stats[2] = (double)(*nonfinite);
-    stats[3] = 0.0;
-    *nonfinite = 0u;
+    if (threadIdx.x == 0) {
+        stats[0] = emax;
+        stats[1] = drift;
+        stats[2] = (double)(*nonfinite);
+        stats[3] = 0.0;
+        *nonfinite = 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -806,26 +817,29 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
     int cur = 0;  // dual field buffer holding the current iterate
     int ucur = 0; // u buffer holding u_s
     for (int s = 0; s <= K; ++s) {
+        // timing: one event pair around the back-to-back Chambolle launches
+        // of this solve (events between launches would perturb them)
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (g_timing.on) {
+            if ((rc = timing_pair(&e0, &e1)) != TVSPEC_OK)
+                return rc;
+            HIP_TRY(hipEventRecord(e0, st));
+        }
         for (int done = 0; done < iters;) {
             // cold start: the first launch of a solve starts from p = 0
             const int zero_in = (!warm && done == 0) ? 1 : 0;
             const int it = (iters - done) < per_launch ? (iters - done) : per_launch;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (g_timing.on) {
-                if ((rc = timing_pair(&e0, &e1)) != TVSPEC_OK)
-                    return rc;
-                HIP_TRY(hipEventRecord(e0, st));
-            }
             hipLaunchKernelGGL(kt, dim3(ntiles, C), dim3(kTileThreads), 0, st, pbuf[cur][0], pbuf[cur][1], gx, gy,
                                pbuf[1 - cur][0], pbuf[1 - cur][1], H, W, ntx, ntiles, (S)tau, it, zero_in);
             if (g_timing.on) {
-                HIP_TRY(hipEventRecord(e1, st));
                 ++g_timing.launches;
                 g_timing.pixel_iters += (long long)n_all * it;
             }
             cur = 1 - cur;
             done += it;
         }
+        if (g_timing.on)
+            HIP_TRY(hipEventRecord(e1, st));
         double *band = s >= 1 ? bands + (size_t)band_of[s] * n_all : nullptr;
         hipLaunchKernelGGL((k_flow_step<S, M>), dim3(nblk, C), dim3(kThreads), 0, st, pbuf[cur][0], pbuf[cur][1],
                            sc.u[ucur], sc.u[1 - ucur], sc.dprev, gx, gy, band, res, sc.spart, H, W, C, s, K, dt);
@@ -835,7 +849,7 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
     hipLaunchKernelGGL(k_check, dim3(nblk, C), dim3(kThreads), 0, st, f, bands, res, sc.u[ucur], plane, C, nb,
                        sc.rpart);
     hipLaunchKernelGGL(k_reduce_s, dim3(K * C), dim3(kThreads), 0, st, sc.spart, C, K, nblk, dt, Sout);
-    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, st, sc.rpart, C, nblk, plane, stats, sc.nonfinite);
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, st, sc.rpart, C, nblk, plane, stats, sc.nonfinite);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -928,7 +942,7 @@ extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
 
     HIP_TRY(hipMemcpyAsync(h.f, f, n_all * sizeof(float), hipMemcpyHostToDevice, h.stream));
     rc = decompose_on_device(h.f, H, W, C, dt, K, inner_iters, band_edges, n_bands, h.bands, h.S, h.res, h.stats,
-                             TVSPEC_DEFAULT_TAU, 1, TVSPEC_DEFAULT_PRECISION, 0, h.stream);
+                             TVSPEC_DEFAULT_TAU, 0, TVSPEC_DEFAULT_PRECISION, 0, h.stream);
     if (rc != TVSPEC_OK)
         return rc;
     HIP_TRY(hipMemcpyAsync(bands, h.bands, nb_n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
