@@ -86,6 +86,31 @@ def cpu_baseline(f, wl):
                       "iterations), %.1f s" % sec}
 
 
+def batch_throughput(n, precision):
+    """One batched call over n seeded 64x64 shape images (dt 0.005, K 60, 200
+    iterations, 4 dyadic bands): MPix/s of the whole batch."""
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import synth, tvspec
+    imgs = np.stack([synth.shapes_image(synth.SMALL_64, 1000 + i) for i in range(n)])
+    f = torch.from_numpy(imgs).to("cuda:0")
+    edges = [[0, 1, 2, 4, 60]] * n
+
+    def call():
+        return tvspec.tvspec_decompose_batch_dev(f, [0.005] * n, [60] * n, 200, edges, precision=precision)
+
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"images": n, "ms_per_batch": ms, "MPix_per_s": n * 64 * 64 / 1e6 / (ms / 1e3),
+            "workload": "64x64 shape images, dt 0.005, K 60, 200 iterations, 4 dyadic bands"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +119,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["f32", "mixed", "f64"])
     ap.add_argument("--iters-per-launch", type=int, default=0)
     ap.add_argument("--latency-calls", type=int, default=20)
+    ap.add_argument("--batch-images", type=int, default=256,
+                    help="also time one batched call over this many 64x64 images (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -215,6 +242,10 @@ def main():
             "kernel_share_of_step": t["kernel_ms"] / ms_per_step,
         }
         print("bench: roofline pass done", file=sys.stderr, flush=True)
+
+    if args.batch_images > 0:
+        rec["batch_64x64"] = batch_throughput(args.batch_images, args.precision)
+        print("bench: batched 64x64 pass done", file=sys.stderr, flush=True)
 
     # the host entry point (host buffers, PCIe-inclusive), once, for reference
     t1 = time.perf_counter()

@@ -135,6 +135,35 @@ int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
                          int precision, int iters_per_launch, void *stream);
 
 /*
+ * Batched device entry point: B images of the same size (H, W, C) and the
+ * same number of Chambolle iterations, each with its own dt, K and band
+ * edges, decomposed in one sequence of launches (every kernel covers all
+ * B*C channel planes; an image whose flow is complete is skipped by later
+ * launches).  Results are those of B separate tvspec_decompose_dev calls
+ * with the same options, bit for bit.
+ *
+ *   f          device, [B][C][H][W] float32
+ *   dt, K      host arrays [B]
+ *   band_edges host, image b's n_bands[b]+1 edges, concatenated in image order
+ *   n_bands    host array [B]
+ *   bands      device, image b's [n_bands[b]][C][H][W] float64 blocks
+ *              concatenated in image order
+ *   S          device, image b's [C][K[b]] float64 blocks concatenated
+ *   residual   device, [B][C][H][W] float64
+ *   stats      device, [B][TVSPEC_NSTATS] float64 (as tvspec_decompose_dev)
+ *   other arguments as tvspec_decompose_dev.
+ *
+ * Ownership and ordering as tvspec_decompose_dev.  Errors: TVSPEC_EINVAL for
+ * B < 1, B*C > 65535, or any image's invalid dt, K, n_bands or edges (the
+ * message names the image), and as tvspec_decompose_dev otherwise.
+ */
+int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int inner_iters,
+                               const double *dt, const int *K, const int *band_edges,
+                               const int *n_bands, double *bands, double *S, double *residual,
+                               double *stats, double tau, int warm_start, int precision,
+                               int iters_per_launch, void *stream);
+
+/*
  * Dyadic band edges (the paper groups unit-step bands dyadically, Sec. 4.1):
  * edges = {0, 1, 2, 4, ..., 2^(B-2), K} for B = n_bands >= 2, {0, K} for
  * B = 1.  `edges` has room for n_bands+1 ints (host memory).

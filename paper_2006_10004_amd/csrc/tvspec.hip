@@ -189,37 +189,54 @@ __device__ __forceinline__ double block_max256(double v, double *sh)
 // ---------------------------------------------------------------------------
 // kernels
 
+// Per-image parameters of a batch (device copy of the descriptor table).
+struct ImageDesc {
+    double dt;          // time step
+    int K;              // spectral samples (K+1 ROF solves)
+    int nbands;         // bands
+    long long band_off; // element offset of the image's bands [nbands][C][H][W]
+    long long s_off;    // element offset of the image's S [C][K]
+    long long row_off;  // offset of the image's band-index row (K+1 ints)
+};
+
+// Zero a float64 buffer (the bands of every image of a batch).
+__global__ __launch_bounds__(kThreads) void k_fill0(double *__restrict__ a, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += stride)
+        a[q] = 0.0;
+}
+
 // u = f, G = grad f / dt (data term of the first solve), p = 0 (buffer A),
-// bands = 0; counts non-finite inputs.
+// every image active; counts non-finite inputs per image.  The buffers hold
+// the B*C channel planes of the batch back to back.
 template <typename S, typename M>
 __global__ __launch_bounds__(kThreads) void k_init(const float *__restrict__ f, double *__restrict__ u,
                                                    M *__restrict__ gx, M *__restrict__ gy, S *__restrict__ px,
-                                                   S *__restrict__ py, double *__restrict__ bands, int H, int W,
-                                                   size_t n_all, int nbands, double dt,
-                                                   unsigned int *__restrict__ nonfinite)
+                                                   S *__restrict__ py, int H, int W, int C, size_t n_all,
+                                                   const ImageDesc *__restrict__ desc,
+                                                   unsigned int *__restrict__ nonfinite, int *__restrict__ active)
 {
-    __shared__ double sh[4];
-    double bad = 0.0;
     const size_t plane = (size_t)H * (size_t)W;
     const size_t stride = (size_t)gridDim.x * kThreads;
     for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n_all; q += stride) {
-        const int qq = (int)(q % plane);
+        const size_t ch = q / plane;
+        const int qq = (int)(q - ch * plane);
+        const int img = (int)(ch / (size_t)C);
         const int i = qq / W;
         const int j = qq - i * W;
+        const double dt = desc[img].dt;
         const float v = f[q];
         if (!isfinite(v))
-            bad += 1.0;
+            atomicAdd(&nonfinite[img], 1u);
+        if (qq == 0 && ch == (size_t)img * C)
+            active[img] = 1;
         u[q] = (double)v;
         gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
         gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
         px[q] = S(0);
         py[q] = S(0);
-        for (int k = 0; k < nbands; ++k)
-            bands[(size_t)k * n_all + q] = 0.0;
     }
-    bad = block_sum256(bad, sh);
-    if (threadIdx.x == 0 && bad > 0.0)
-        atomicAdd(nonfinite, (unsigned int)bad);
 }
 
 // Temporally blocked Chambolle iterations.
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_init(const float *__restrict__ f, 
 // the small gradients of flat regions, whereas G carries only the relative
 // rounding of the gradient itself.
 //
-// Grid: (number of BX x BY output tiles, C); 1024 threads, so that every
+// Grid: (number of BX x BY output tiles, B*C); 1024 threads, so that every
 // SIMD of the CU has four waves to interleave (the per-pixel chain of LDS
 // reads, square root and reciprocal is long and a tile holds few pixels).
 // The workgroup stages the (BX+2TB) x (BY+2TB) region around its tile: the
@@ -250,7 +267,8 @@ __global__ __launch_bounds__(kThreads) void k_init(const float *__restrict__ f, 
 // that realises the Neumann divergence (p_x = 0 on the last column and
 // p_y = 0 on the last row is preserved by the update because a_x, a_y vanish
 // there).  With zero_in set (first launch of a cold-started solve) the
-// incoming dual field is taken as zero instead of being read.  A region
+// incoming dual field is taken as zero instead of being read.  Channel planes
+// of images whose flow is complete (active flag 0) are skipped.  A region
 // pixel at distance e from the region edge is exact while the iteration
 // count is <= e, so after iters <= TB iterations the BX x BY centre is exact
 // and is written.
@@ -259,8 +277,11 @@ constexpr int kTileThreads = 1024;
 template <typename S, typename M, int BX, int BY, int TB>
 __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(
     const S *__restrict__ pxi, const S *__restrict__ pyi, const M *__restrict__ gxi, const M *__restrict__ gyi,
-    S *__restrict__ pxo, S *__restrict__ pyo, int H, int W, int ntx, int ntiles, S tau, int iters, int zero_in)
+    S *__restrict__ pxo, S *__restrict__ pyo, int H, int W, int ntx, int ntiles, S tau, int iters, int zero_in,
+    const int *__restrict__ active, int C)
 {
+    if (!active[blockIdx.y / C])
+        return;
     constexpr int RX = BX + 2 * TB;
     constexpr int RY = BY + 2 * TB;
     constexpr int RN = RX * RY;
@@ -406,12 +427,15 @@ __device__ __forceinline__ double div_p(const S *__restrict__ px, const S *__res
 }
 
 // Outer step s of the flow, fused with the spectral transform.
-// Grid: (nblk, C), nblk fixed per image size so partial sums are reproducible.
+// Grid: (nblk, B*C), nblk fixed per image size so partial sums are
+// reproducible; channel plane y belongs to image y / C.  Per image:
+//   s > K:  nothing (the image's flow is complete)
 //   D_s     = dt div p                     (u_s - u_{s+1})
 //   u_{s+1} = u_s - D_s                    (written to the other u buffer)
 //   s >= 1: phi_s dt = s (D_{s-1} - D_s)   added to the band holding s
 //           spart  <- block sum of |D_{s-1} - D_s|   (S(t_s) = s/dt * total)
-//   s == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t)
+//   s == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t),
+//           and the image is marked complete for the tile kernel
 //   G       = grad(u_{s+1}) / dt           (data term of the next solve; the
 //             right and lower neighbours' u_{s+1} are recomputed here with
 //             the same operations their own threads use, so they match bit
@@ -420,14 +444,23 @@ template <typename S, typename M>
 __global__ __launch_bounds__(kThreads) void k_flow_step(const S *__restrict__ px, const S *__restrict__ py,
                                                         const double *__restrict__ uin, double *__restrict__ uout,
                                                         double *__restrict__ dprev, M *__restrict__ gx,
-                                                        M *__restrict__ gy, double *__restrict__ band,
+                                                        M *__restrict__ gy, double *__restrict__ bands,
                                                         double *__restrict__ resid, double *__restrict__ spart,
-                                                        int H, int W, int C, int k, int K, double dt)
+                                                        const ImageDesc *__restrict__ desc,
+                                                        const int *__restrict__ band_rows, int *__restrict__ active,
+                                                        int H, int W, int C, int BC, int k)
 {
     __shared__ double sh[4];
-    const int c = blockIdx.y;
+    const int y = blockIdx.y;
+    const int img = y / C;
+    const int c = y - img * C;
+    const ImageDesc dsc = desc[img];
+    if (k > dsc.K)
+        return;
+    const double dt = dsc.dt;
+    const int K = dsc.K;
     const int plane = H * W;
-    const size_t coff = (size_t)c * (size_t)plane;
+    const size_t coff = (size_t)y * (size_t)plane;
     px += coff;
     py += coff;
     uin += coff;
@@ -435,6 +468,10 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const S *__restrict__ px
     dprev += coff;
     gx += coff;
     gy += coff;
+    resid += coff;
+    double *band = nullptr;
+    if (k >= 1)
+        band = bands + dsc.band_off + ((size_t)band_rows[dsc.row_off + k] * C + c) * (size_t)plane;
     const double kd = (double)k;
     double acc = 0.0;
     for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
@@ -445,11 +482,11 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const S *__restrict__ px
         const double un = uo - D;
         if (k >= 1) {
             const double dl = dprev[q] - D;
-            band[coff + q] += kd * dl;
+            band[q] += kd * dl;
             acc += fabs(dl);
         }
         if (k == K)
-            resid[coff + q] = uo + (double)K * D;
+            resid[q] = uo + (double)K * D;
         uout[q] = un;
         dprev[q] = D;
         if (j < W - 1) {
@@ -468,71 +505,90 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const S *__restrict__ px
     if (k >= 1) {
         acc = block_sum256(acc, sh);
         if (threadIdx.x == 0)
-            spart[((size_t)(k - 1) * C + c) * gridDim.x + blockIdx.x] = acc;
+            spart[((size_t)(k - 1) * BC + y) * gridDim.x + blockIdx.x] = acc;
     }
+    if (k == K && c == 0 && blockIdx.x == 0 && threadIdx.x == 0)
+        active[img] = 0;
 }
 
 // Per-block partials of: max |f - sum_j b_j - r|, sum u_{K+1}, sum f.
+// Grid: (nblk, B*C).
+// u_{K+1} of an image is in u0 or u1 by the parity of K + 1 (step s writes
+// u_{s+1} to buffer (s + 1) mod 2, and steps after the image's K are skipped).
 __global__ __launch_bounds__(kThreads) void k_check(const float *__restrict__ f, const double *__restrict__ bands,
-                                                    const double *__restrict__ resid, const double *__restrict__ u,
-                                                    int plane, int C, int nbands, double *__restrict__ rpart)
+                                                    const double *__restrict__ resid, const double *__restrict__ u0,
+                                                    const double *__restrict__ u1,
+                                                    const ImageDesc *__restrict__ desc, int plane, int C,
+                                                    double *__restrict__ rpart)
 {
     __shared__ double sh[4];
-    const int c = blockIdx.y;
-    const size_t coff = (size_t)c * (size_t)plane;
-    const size_t n_all = (size_t)C * (size_t)plane;
+    const int y = blockIdx.y;
+    const int img = y / C;
+    const int c = y - img * C;
+    const ImageDesc dsc = desc[img];
+    const double *u = ((dsc.K + 1) & 1) ? u1 : u0;
+    const size_t coff = (size_t)y * (size_t)plane;
+    const double *b0 = bands + dsc.band_off + (size_t)c * plane;
+    const size_t bstride = (size_t)C * (size_t)plane;
     double emax = 0.0, su = 0.0, sf = 0.0;
     for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
-        const size_t g = coff + q;
         double acc = 0.0;
-        for (int j = 0; j < nbands; ++j)
-            acc += bands[(size_t)j * n_all + g];
-        const double fv = (double)f[g];
-        emax = fmax(emax, fabs(fv - acc - resid[g]));
-        su += u[g];
+        for (int j = 0; j < dsc.nbands; ++j)
+            acc += b0[(size_t)j * bstride + q];
+        const double fv = (double)f[coff + q];
+        emax = fmax(emax, fabs(fv - acc - resid[coff + q]));
+        su += u[coff + q];
         sf += fv;
     }
     emax = block_max256(emax, sh);
     su = block_sum256(su, sh);
     sf = block_sum256(sf, sh);
     if (threadIdx.x == 0) {
-        double *o = rpart + ((size_t)c * gridDim.x + blockIdx.x) * 3;
+        double *o = rpart + ((size_t)y * gridDim.x + blockIdx.x) * 3;
         o[0] = emax;
         o[1] = su;
         o[2] = sf;
     }
 }
 
-// S[c][k-1] = k/dt * (sum of the step partials of sample k, channel c):
-// one block per (k, c), each thread summing a fixed stride of partials,
-// then the block sum in a fixed order.
-__global__ __launch_bounds__(kThreads) void k_reduce_s(const double *__restrict__ spart, int C, int K, int nblk,
-                                                       double dt, double *__restrict__ S)
+// S of image b, channel c, sample k: k/dt * (sum of the step partials),
+// one block per (k, channel plane), each thread summing a fixed stride of
+// partials, then the block sum in a fixed order.  Grid: (Kmax, B*C).
+__global__ __launch_bounds__(kThreads) void k_reduce_s(const double *__restrict__ spart,
+                                                       const ImageDesc *__restrict__ desc, int C, int BC, int nblk,
+                                                       double *__restrict__ S)
 {
     __shared__ double sh[4];
-    const int t = blockIdx.x;            // (k-1) * C + c
-    const int k = t / C + 1;
-    const int c = t - (k - 1) * C;
-    const double *p = spart + (size_t)t * nblk;
+    const int k = blockIdx.x + 1;
+    const int y = blockIdx.y;
+    const int img = y / C;
+    const int c = y - img * C;
+    const ImageDesc dsc = desc[img];
+    if (k > dsc.K)
+        return;
+    const double *p = spart + ((size_t)(k - 1) * BC + y) * nblk;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kThreads)
         s += p[b];
     s = block_sum256(s, sh);
     if (threadIdx.x == 0)
-        S[(size_t)c * K + (k - 1)] = s * ((double)k / dt);
+        S[dsc.s_off + (size_t)c * dsc.K + (k - 1)] = s * ((double)k / dsc.dt);
 }
 
-// One block: the report from the check partials (fixed reduction order).
+// The report of image blockIdx.x from the check partials (fixed reduction
+// order); clears the image's non-finite counter.
 __global__ __launch_bounds__(kThreads) void k_report(const double *__restrict__ rpart, int C, int nblk_chk,
                                                      int plane, double *__restrict__ stats,
                                                      unsigned int *__restrict__ nonfinite)
 {
     __shared__ double sh[4];
+    const int img = blockIdx.x;
     double emax = 0.0, drift = 0.0;
     for (int c = 0; c < C; ++c) {
+        const int y = img * C + c;
         double e = 0.0, su = 0.0, sf = 0.0;
         for (int b = threadIdx.x; b < nblk_chk; b += kThreads) {
-            const double *o = rpart + ((size_t)c * nblk_chk + b) * 3;
+            const double *o = rpart + ((size_t)y * nblk_chk + b) * 3;
             e = fmax(e, o[0]);
             su += o[1];
             sf += o[2];
@@ -544,11 +600,12 @@ __global__ __launch_bounds__(kThreads) void k_report(const double *__restrict__ 
         drift = fmax(drift, fabs(su / (double)plane - sf / (double)plane));
     }
     if (threadIdx.x == 0) {
-        stats[0] = emax;
-        stats[1] = drift;
-        stats[2] = (double)(*nonfinite);
-        stats[3] = 0.0;
-        *nonfinite = 0u;
+        double *st = stats + (size_t)img * TVSPEC_NSTATS;
+        st[0] = emax;
+        st[1] = drift;
+        st[2] = (double)nonfinite[img];
+        st[3] = 0.0;
+        nonfinite[img] = 0u;
     }
 }
 
@@ -571,7 +628,8 @@ int blocks_for(size_t n, int cap)
 int plane_blocks(int plane) { return blocks_for((size_t)plane, 1024); }
 
 template <typename S, typename M>
-using TileKernel = void (*)(const S *, const S *, const M *, const M *, S *, S *, int, int, int, int, S, int, int);
+using TileKernel = void (*)(const S *, const S *, const M *, const M *, S *, S *, int, int, int, int, S, int, int,
+                            const int *, int);
 
 // Largest temporal blocking factor compiled for a mode (LDS and registers of
 // the (32+2TB)^2 region, which are sized by the dual-field type S).
@@ -594,9 +652,11 @@ template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 // device scratch, cached per (device, precision mode) and grown on demand
 
 struct Scratch {
-    size_t n_all = 0;                  // C*H*W the plane buffers hold
+    size_t n_all = 0;                  // B*C*H*W the plane buffers hold
     size_t spart_n = 0;                // doubles in spart
     size_t rpart_n = 0;                // doubles in rpart
+    size_t nimg = 0;                   // images the per-image buffers hold
+    size_t rows_n = 0;                 // ints in band_rows
     void *pa[2] = {nullptr, nullptr};  // dual field buffer A: px, py (type S)
     void *pb[2] = {nullptr, nullptr};  // dual field buffer B: px, py (type S)
     void *g[2] = {nullptr, nullptr};   // G = grad(g)/dt: x and y planes (type M)
@@ -604,7 +664,19 @@ struct Scratch {
     double *dprev = nullptr;
     double *spart = nullptr;
     double *rpart = nullptr;
-    unsigned int *nonfinite = nullptr;
+    ImageDesc *desc = nullptr;         // per image
+    int *band_rows = nullptr;          // band index of every sample, per image
+    int *active = nullptr;             // per image: flow not yet complete
+    unsigned int *nonfinite = nullptr; // per image
+};
+
+// Pinned host staging of the descriptor table, and an event marking the
+// upload that last read it (the next call waits for it before rewriting).
+struct DescStage {
+    size_t bytes = 0;
+    char *host = nullptr;
+    hipEvent_t uploaded = nullptr;
+    bool pending = false;
 };
 
 struct HostStage {
@@ -618,9 +690,10 @@ constexpr int kMaxDevices = 64;
 constexpr int kModes = 3;
 std::mutex g_mu;
 Scratch g_scratch[kMaxDevices][kModes];
+DescStage g_desc_stage[kMaxDevices];
 HostStage g_stage[kMaxDevices];
 
-// Benchmark timing of the Chambolle kernel: event pairs around each launch.
+// Benchmark timing of the Chambolle kernel: one event pair per ROF solve.
 struct Timing {
     bool on = false;
     std::vector<hipEvent_t> ev; // start, stop, start, stop, ...
@@ -645,7 +718,7 @@ int timing_drain()
     return TVSPEC_OK;
 }
 
-// Event pair for the next launch (created on demand, recycled after a drain).
+// Event pair for the next solve (created on demand, recycled after a drain).
 int timing_pair(hipEvent_t *a, hipEvent_t *b)
 {
     if (g_timing.used == kMaxTimingPairs) {
@@ -688,8 +761,11 @@ void free_scratch(Scratch &s)
     free_typed(s.dprev);
     free_typed(s.spart);
     free_typed(s.rpart);
+    free_typed(s.desc);
+    free_typed(s.band_rows);
+    free_typed(s.active);
     free_typed(s.nonfinite);
-    s.n_all = s.spart_n = s.rpart_n = 0;
+    s.n_all = s.spart_n = s.rpart_n = s.nimg = s.rows_n = 0;
 }
 
 void free_stage(HostStage &h)
@@ -702,12 +778,30 @@ void free_stage(HostStage &h)
     h.f_n = h.bands_n = h.s_n = h.r_n = 0;
 }
 
-int ensure_scratch(Scratch &s, size_t elem_s, size_t elem_m, size_t n_all, size_t spart_n, size_t rpart_n)
+void free_desc_stage(DescStage &d)
 {
-    if (s.n_all >= n_all && s.spart_n >= spart_n && s.rpart_n >= rpart_n && s.u[0])
+    if (d.pending && d.uploaded)
+        (void)hipEventSynchronize(d.uploaded);
+    if (d.host)
+        (void)hipHostFree(d.host);
+    if (d.uploaded)
+        (void)hipEventDestroy(d.uploaded);
+    d = DescStage();
+}
+
+int ensure_scratch(Scratch &s, size_t elem_s, size_t elem_m, size_t n_all, size_t spart_n, size_t rpart_n,
+                   size_t nimg, size_t rows_n)
+{
+    if (s.n_all >= n_all && s.spart_n >= spart_n && s.rpart_n >= rpart_n && s.nimg >= nimg && s.rows_n >= rows_n &&
+        s.u[0])
         return TVSPEC_OK;
     // buffers may still be in use by earlier enqueued work
     HIP_TRY(hipDeviceSynchronize());
+    n_all = n_all > s.n_all ? n_all : s.n_all;
+    spart_n = spart_n > s.spart_n ? spart_n : s.spart_n;
+    rpart_n = rpart_n > s.rpart_n ? rpart_n : s.rpart_n;
+    nimg = nimg > s.nimg ? nimg : s.nimg;
+    rows_n = rows_n > s.rows_n ? rows_n : s.rows_n;
     free_scratch(s);
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(hipMalloc(&s.pa[i], n_all * elem_s));
@@ -718,37 +812,56 @@ int ensure_scratch(Scratch &s, size_t elem_s, size_t elem_m, size_t n_all, size_
     HIP_TRY(hipMalloc((void **)&s.dprev, n_all * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s.spart, spart_n * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s.rpart, rpart_n * sizeof(double)));
-    HIP_TRY(hipMalloc((void **)&s.nonfinite, sizeof(unsigned int)));
-    HIP_TRY(hipMemset(s.nonfinite, 0, sizeof(unsigned int)));
+    HIP_TRY(hipMalloc((void **)&s.desc, nimg * sizeof(ImageDesc)));
+    HIP_TRY(hipMalloc((void **)&s.band_rows, rows_n * sizeof(int)));
+    HIP_TRY(hipMalloc((void **)&s.active, nimg * sizeof(int)));
+    HIP_TRY(hipMalloc((void **)&s.nonfinite, nimg * sizeof(unsigned int)));
+    HIP_TRY(hipMemset(s.nonfinite, 0, nimg * sizeof(unsigned int)));
     HIP_TRY(hipDeviceSynchronize());
     s.n_all = n_all;
     s.spart_n = spart_n;
     s.rpart_n = rpart_n;
+    s.nimg = nimg;
+    s.rows_n = rows_n;
+    return TVSPEC_OK;
+}
+
+// Copy the descriptor table and band rows to the device through the pinned
+// staging buffer, ordered on stream st.
+int upload_desc(int dev, const std::vector<ImageDesc> &desc, const std::vector<int> &rows, Scratch &sc,
+                hipStream_t st)
+{
+    DescStage &d = g_desc_stage[dev];
+    const size_t nd = desc.size() * sizeof(ImageDesc);
+    const size_t nr = rows.size() * sizeof(int);
+    if (d.pending) {
+        HIP_TRY(hipEventSynchronize(d.uploaded));
+        d.pending = false;
+    }
+    if (d.bytes < nd + nr) {
+        if (d.host)
+            HIP_TRY(hipHostFree(d.host));
+        d.host = nullptr;
+        d.bytes = 0;
+        HIP_TRY(hipHostMalloc((void **)&d.host, nd + nr, hipHostMallocDefault));
+        d.bytes = nd + nr;
+    }
+    if (!d.uploaded)
+        HIP_TRY(hipEventCreateWithFlags(&d.uploaded, hipEventDisableTiming));
+    std::memcpy(d.host, desc.data(), nd);
+    std::memcpy(d.host + nd, rows.data(), nr);
+    HIP_TRY(hipMemcpyAsync(sc.desc, d.host, nd, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sc.band_rows, d.host + nd, nr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(d.uploaded, st));
+    d.pending = true;
     return TVSPEC_OK;
 }
 
 // ---------------------------------------------------------------------------
 // argument validation (host only, before any device call)
 
-int validate(const void *f, int H, int W, int C, double dt, int K, int iters, const int *edges, int nb,
-             const void *bands, const void *S, const void *res)
+int validate_edges(const int *edges, int nb, int K)
 {
-    if (!f || !bands || !S || !res || !edges)
-        return fail(TVSPEC_EINVAL, "null pointer argument");
-    if (H < 2 || W < 2)
-        return fail(TVSPEC_EINVAL, "H and W must be >= 2");
-    if (C < 1)
-        return fail(TVSPEC_EINVAL, "C must be >= 1");
-    if ((long long)H * (long long)W > (1LL << 30))
-        return fail(TVSPEC_EINVAL, "H*W must be <= 2^30");
-    if ((long long)H * W * C > (1LL << 40))
-        return fail(TVSPEC_EINVAL, "C*H*W too large");
-    if (!std::isfinite(dt) || !(dt > 0.0))
-        return fail(TVSPEC_EINVAL, "dt must be finite and > 0");
-    if (K < 1)
-        return fail(TVSPEC_EINVAL, "K must be >= 1");
-    if (iters < 1)
-        return fail(TVSPEC_EINVAL, "inner_iters must be >= 1");
     if (nb < 1 || nb > K)
         return fail(TVSPEC_EINVAL, "n_bands must be in [1, K]");
     if (edges[0] != 0 || edges[nb] != K)
@@ -757,6 +870,34 @@ int validate(const void *f, int H, int W, int C, double dt, int K, int iters, co
         if (edges[j] <= edges[j - 1])
             return fail(TVSPEC_EINVAL, "band edges must be strictly increasing");
     return TVSPEC_OK;
+}
+
+int validate_shape(int B, int H, int W, int C, int iters)
+{
+    if (B < 1)
+        return fail(TVSPEC_EINVAL, "B must be >= 1");
+    if (H < 2 || W < 2)
+        return fail(TVSPEC_EINVAL, "H and W must be >= 2");
+    if (C < 1)
+        return fail(TVSPEC_EINVAL, "C must be >= 1");
+    if ((long long)B * C > 65535)
+        return fail(TVSPEC_EINVAL, "B*C must be <= 65535");
+    if ((long long)H * (long long)W > (1LL << 30))
+        return fail(TVSPEC_EINVAL, "H*W must be <= 2^30");
+    if ((long long)H * W * C * B > (1LL << 40))
+        return fail(TVSPEC_EINVAL, "B*C*H*W too large");
+    if (iters < 1)
+        return fail(TVSPEC_EINVAL, "inner_iters must be >= 1");
+    return TVSPEC_OK;
+}
+
+int validate_image(double dt, int K, const int *edges, int nb)
+{
+    if (!std::isfinite(dt) || !(dt > 0.0))
+        return fail(TVSPEC_EINVAL, "dt must be finite and > 0");
+    if (K < 1)
+        return fail(TVSPEC_EINVAL, "K must be >= 1");
+    return validate_edges(edges, nb, K);
 }
 
 int validate_opts(double tau, int warm, int precision, int ipl)
@@ -775,20 +916,57 @@ int validate_opts(double tau, int warm, int precision, int ipl)
 }
 
 // ---------------------------------------------------------------------------
-// the decomposition, enqueued on a stream
+// the decomposition of a batch of equal-size images, enqueued on a stream
 
-template <typename S, typename M>
-int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, const int *edges, int nb,
-            double *bands, double *Sout, double *res, double *stats, double tau, int warm, int ipl,
-            hipStream_t st, Scratch &sc)
+struct Batch {
+    const float *f;
+    int B, H, W, C, iters;
+    const double *dt;   // host [B]
+    const int *K;       // host [B]
+    const int *edges;   // host, concatenated n_bands[b]+1 entries per image
+    const int *nb;      // host [B]
+    double *bands, *S, *res, *stats;
+    double tau;
+    int warm, ipl;
+    hipStream_t st;
+};
+
+template <typename S, typename M> int enqueue(int dev, const Batch &a, Scratch &sc)
 {
-    const int plane = H * W;
-    const size_t n_all = (size_t)plane * (size_t)C;
+    const int plane = a.H * a.W;
+    const int BC = a.B * a.C;
+    const size_t n_all = (size_t)plane * (size_t)BC;
     const int nblk = plane_blocks(plane);
-    const size_t spart_n = (size_t)K * C * nblk;
-    const size_t rpart_n = (size_t)C * nblk * 3;
-    int rc = ensure_scratch(sc, sizeof(S), sizeof(M), n_all, spart_n, rpart_n);
+
+    // descriptor table, band index rows, output offsets
+    std::vector<ImageDesc> desc(a.B);
+    std::vector<int> rows;
+    int Kmax = 0;
+    long long band_off = 0, s_off = 0;
+    for (int b = 0, e0 = 0; b < a.B; ++b) {
+        const int K = a.K[b], nb = a.nb[b];
+        desc[b].dt = a.dt[b];
+        desc[b].K = K;
+        desc[b].nbands = nb;
+        desc[b].band_off = band_off;
+        desc[b].s_off = s_off;
+        desc[b].row_off = (long long)rows.size();
+        const int *e = a.edges + e0;
+        rows.push_back(0); // sample 0 carries no phi
+        for (int j = 0; j < nb; ++j)
+            for (int k = e[j] + 1; k <= e[j + 1]; ++k)
+                rows.push_back(j);
+        band_off += (long long)nb * a.C * plane;
+        s_off += (long long)a.C * K;
+        e0 += nb + 1;
+        Kmax = K > Kmax ? K : Kmax;
+    }
+    const size_t spart_n = (size_t)Kmax * BC * nblk;
+    const size_t rpart_n = (size_t)BC * nblk * 3;
+    int rc = ensure_scratch(sc, sizeof(S), sizeof(M), n_all, spart_n, rpart_n, (size_t)a.B, rows.size());
     if (rc != TVSPEC_OK)
+        return rc;
+    if ((rc = upload_desc(dev, desc, rows, sc, a.st)) != TVSPEC_OK)
         return rc;
 
     S *pbuf[2][2] = {{(S *)sc.pa[0], (S *)sc.pa[1]}, {(S *)sc.pb[0], (S *)sc.pb[1]}};
@@ -796,67 +974,65 @@ int enqueue(const float *f, int H, int W, int C, double dt, int K, int iters, co
     M *gy = (M *)sc.g[1];
 
     int tb = 0;
-    const int want = ipl > 0 ? ipl : 8;
+    const int want = a.ipl > 0 ? a.ipl : 8;
     TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
-    const int ntx = (W + kTileX - 1) / kTileX;
-    const int nty = (H + kTileY - 1) / kTileY;
+    const int ntx = (a.W + kTileX - 1) / kTileX;
+    const int nty = (a.H + kTileY - 1) / kTileY;
     const int ntiles = ntx * nty;
-    const int per_launch = ipl > 0 ? ipl : tb;
+    const int per_launch = a.ipl > 0 ? a.ipl : tb;
 
-    // band index of every sample k = 1..K
-    std::vector<int> band_of(K + 1, 0);
-    for (int j = 0; j < nb; ++j)
-        for (int k = edges[j] + 1; k <= edges[j + 1]; ++k)
-            band_of[k] = j;
-
-    const int gblk = blocks_for(n_all, 4096);
-    hipLaunchKernelGGL((k_init<S, M>), dim3(gblk), dim3(kThreads), 0, st, f, sc.u[0], gx, gy, pbuf[0][0],
-                       pbuf[0][1], bands, H, W, n_all, nb, dt, sc.nonfinite);
+    hipLaunchKernelGGL(k_fill0, dim3(blocks_for((size_t)band_off, 4096)), dim3(kThreads), 0, a.st, a.bands,
+                       (size_t)band_off);
+    hipLaunchKernelGGL((k_init<S, M>), dim3(blocks_for(n_all, 4096)), dim3(kThreads), 0, a.st, a.f, sc.u[0], gx, gy,
+                       pbuf[0][0], pbuf[0][1], a.H, a.W, a.C, n_all, sc.desc, sc.nonfinite, sc.active);
     HIP_TRY(hipGetLastError());
 
     int cur = 0;  // dual field buffer holding the current iterate
-    int ucur = 0; // u buffer holding u_s
-    for (int s = 0; s <= K; ++s) {
+    int ucur = 0; // u buffer holding u_s (= s mod 2)
+    for (int s = 0; s <= Kmax; ++s) {
         // timing: one event pair around the back-to-back Chambolle launches
         // of this solve (events between launches would perturb them)
         hipEvent_t e0 = nullptr, e1 = nullptr;
+        long long live_planes = 0;
         if (g_timing.on) {
+            for (int b = 0; b < a.B; ++b)
+                live_planes += (s <= a.K[b]) ? a.C : 0;
             if ((rc = timing_pair(&e0, &e1)) != TVSPEC_OK)
                 return rc;
-            HIP_TRY(hipEventRecord(e0, st));
+            HIP_TRY(hipEventRecord(e0, a.st));
         }
-        for (int done = 0; done < iters;) {
+        for (int done = 0; done < a.iters;) {
             // cold start: the first launch of a solve starts from p = 0
-            const int zero_in = (!warm && done == 0) ? 1 : 0;
-            const int it = (iters - done) < per_launch ? (iters - done) : per_launch;
-            hipLaunchKernelGGL(kt, dim3(ntiles, C), dim3(kTileThreads), 0, st, pbuf[cur][0], pbuf[cur][1], gx, gy,
-                               pbuf[1 - cur][0], pbuf[1 - cur][1], H, W, ntx, ntiles, (S)tau, it, zero_in);
+            const int zero_in = (!a.warm && done == 0) ? 1 : 0;
+            const int it = (a.iters - done) < per_launch ? (a.iters - done) : per_launch;
+            hipLaunchKernelGGL(kt, dim3(ntiles, BC), dim3(kTileThreads), 0, a.st, pbuf[cur][0], pbuf[cur][1], gx, gy,
+                               pbuf[1 - cur][0], pbuf[1 - cur][1], a.H, a.W, ntx, ntiles, (S)a.tau, it, zero_in,
+                               sc.active, a.C);
             if (g_timing.on) {
                 ++g_timing.launches;
-                g_timing.pixel_iters += (long long)n_all * it;
+                g_timing.pixel_iters += live_planes * plane * it;
             }
             cur = 1 - cur;
             done += it;
         }
         if (g_timing.on)
-            HIP_TRY(hipEventRecord(e1, st));
-        double *band = s >= 1 ? bands + (size_t)band_of[s] * n_all : nullptr;
-        hipLaunchKernelGGL((k_flow_step<S, M>), dim3(nblk, C), dim3(kThreads), 0, st, pbuf[cur][0], pbuf[cur][1],
-                           sc.u[ucur], sc.u[1 - ucur], sc.dprev, gx, gy, band, res, sc.spart, H, W, C, s, K, dt);
+            HIP_TRY(hipEventRecord(e1, a.st));
+        hipLaunchKernelGGL((k_flow_step<S, M>), dim3(nblk, BC), dim3(kThreads), 0, a.st, pbuf[cur][0], pbuf[cur][1],
+                           sc.u[ucur], sc.u[1 - ucur], sc.dprev, gx, gy, a.bands, a.res, sc.spart, sc.desc,
+                           sc.band_rows, sc.active, a.H, a.W, a.C, BC, s);
         ucur = 1 - ucur;
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_check, dim3(nblk, C), dim3(kThreads), 0, st, f, bands, res, sc.u[ucur], plane, C, nb,
-                       sc.rpart);
-    hipLaunchKernelGGL(k_reduce_s, dim3(K * C), dim3(kThreads), 0, st, sc.spart, C, K, nblk, dt, Sout);
-    hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, st, sc.rpart, C, nblk, plane, stats, sc.nonfinite);
+    hipLaunchKernelGGL(k_check, dim3(nblk, BC), dim3(kThreads), 0, a.st, a.f, a.bands, a.res, sc.u[0], sc.u[1],
+                       sc.desc, plane, a.C, sc.rpart);
+    hipLaunchKernelGGL(k_reduce_s, dim3(Kmax, BC), dim3(kThreads), 0, a.st, sc.spart, sc.desc, a.C, BC, nblk, a.S);
+    hipLaunchKernelGGL(k_report, dim3(a.B), dim3(kThreads), 0, a.st, sc.rpart, a.C, nblk, plane, a.stats,
+                       sc.nonfinite);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
 
-int decompose_on_device(const float *f, int H, int W, int C, double dt, int K, int iters, const int *edges, int nb,
-                        double *bands, double *S, double *res, double *stats, double tau, int warm, int precision,
-                        int ipl, hipStream_t st)
+int decompose_on_device(const Batch &a, int precision)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -865,14 +1041,11 @@ int decompose_on_device(const float *f, int H, int W, int C, double dt, int K, i
     Scratch &sc = g_scratch[dev][precision];
     switch (precision) {
     case TVSPEC_PRECISION_F32:
-        return enqueue<float, float>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
-                                     sc);
+        return enqueue<float, float>(dev, a, sc);
     case TVSPEC_PRECISION_F64:
-        return enqueue<double, double>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
-                                       sc);
+        return enqueue<double, double>(dev, a, sc);
     default:
-        return enqueue<double, float>(f, H, W, C, dt, K, iters, edges, nb, bands, S, res, stats, tau, warm, ipl, st,
-                                      sc);
+        return enqueue<double, float>(dev, a, sc);
     }
 }
 
@@ -892,31 +1065,65 @@ template <typename T> int grow(T *&p, size_t &cap, size_t n)
 // ---------------------------------------------------------------------------
 // C ABI
 
+extern "C" int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int inner_iters,
+                                          const double *dt, const int *K, const int *band_edges, const int *n_bands,
+                                          double *bands, double *S, double *residual, double *stats, double tau,
+                                          int warm_start, int precision, int iters_per_launch, void *stream)
+{
+    g_last_error.clear();
+    if (!f || !dt || !K || !band_edges || !n_bands || !bands || !S || !residual || !stats)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    int rc = validate_shape(B, H, W, C, inner_iters);
+    if (rc != TVSPEC_OK)
+        return rc;
+    for (int b = 0, e0 = 0; b < B; ++b) {
+        if (n_bands[b] < 1 || n_bands[b] > K[b] || K[b] < 1)
+            return fail(TVSPEC_EINVAL, "image " + std::to_string(b) + ": need K >= 1 and 1 <= n_bands <= K");
+        if ((rc = validate_image(dt[b], K[b], band_edges + e0, n_bands[b])) != TVSPEC_OK)
+            return fail(rc, "image " + std::to_string(b) + ": " + g_last_error);
+        e0 += n_bands[b] + 1;
+    }
+    rc = validate_opts(tau, warm_start, precision, iters_per_launch);
+    if (rc != TVSPEC_OK)
+        return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Batch a{f, B, H, W, C, inner_iters, dt, K, band_edges, n_bands, bands, S, residual, stats, tau, warm_start,
+            iters_per_launch, (hipStream_t)stream};
+    return decompose_on_device(a, precision);
+}
+
 extern "C" int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
                                     const int *band_edges, int n_bands, double *bands, double *S, double *residual,
                                     double *stats, double tau, int warm_start, int precision, int iters_per_launch,
                                     void *stream)
 {
     g_last_error.clear();
-    int rc = validate(f, H, W, C, dt, K, inner_iters, band_edges, n_bands, bands, S, residual);
+    if (!f || !band_edges || !bands || !S || !residual || !stats)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    int rc = validate_shape(1, H, W, C, inner_iters);
     if (rc != TVSPEC_OK)
         return rc;
-    if (!stats)
-        return fail(TVSPEC_EINVAL, "null stats pointer");
+    if ((rc = validate_image(dt, K, band_edges, n_bands)) != TVSPEC_OK)
+        return rc;
     rc = validate_opts(tau, warm_start, precision, iters_per_launch);
     if (rc != TVSPEC_OK)
         return rc;
     std::lock_guard<std::mutex> lock(g_mu);
-    return decompose_on_device(f, H, W, C, dt, K, inner_iters, band_edges, n_bands, bands, S, residual, stats, tau,
-                               warm_start, precision, iters_per_launch, (hipStream_t)stream);
+    Batch a{f, 1, H, W, C, inner_iters, &dt, &K, band_edges, &n_bands, bands, S, residual, stats, tau, warm_start,
+            iters_per_launch, (hipStream_t)stream};
+    return decompose_on_device(a, precision);
 }
 
 extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
                                 const int *band_edges, int n_bands, double *bands, double *S, double *residual)
 {
     g_last_error.clear();
-    int rc = validate(f, H, W, C, dt, K, inner_iters, band_edges, n_bands, bands, S, residual);
+    if (!f || !band_edges || !bands || !S || !residual)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    int rc = validate_shape(1, H, W, C, inner_iters);
     if (rc != TVSPEC_OK)
+        return rc;
+    if ((rc = validate_image(dt, K, band_edges, n_bands)) != TVSPEC_OK)
         return rc;
     const size_t n_all = (size_t)H * W * C;
     for (size_t q = 0; q < n_all; ++q)
@@ -941,8 +1148,9 @@ extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
         HIP_TRY(hipMalloc((void **)&h.stats, TVSPEC_NSTATS * sizeof(double)));
 
     HIP_TRY(hipMemcpyAsync(h.f, f, n_all * sizeof(float), hipMemcpyHostToDevice, h.stream));
-    rc = decompose_on_device(h.f, H, W, C, dt, K, inner_iters, band_edges, n_bands, h.bands, h.S, h.res, h.stats,
-                             TVSPEC_DEFAULT_TAU, 0, TVSPEC_DEFAULT_PRECISION, 0, h.stream);
+    Batch a{h.f, 1, H, W, C, inner_iters, &dt, &K, band_edges, &n_bands, h.bands, h.S, h.res, h.stats,
+            TVSPEC_DEFAULT_TAU, 0, 0, h.stream};
+    rc = decompose_on_device(a, TVSPEC_DEFAULT_PRECISION);
     if (rc != TVSPEC_OK)
         return rc;
     HIP_TRY(hipMemcpyAsync(bands, h.bands, nb_n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
@@ -1008,7 +1216,7 @@ extern "C" void tvspec_release(void)
     if (hipGetDeviceCount(&ndev) != hipSuccess)
         return;
     for (int d = 0; d < ndev && d < kMaxDevices; ++d) {
-        bool any = g_stage[d].stream || g_stage[d].f;
+        bool any = g_stage[d].stream || g_stage[d].f || g_desc_stage[d].host;
         for (int m = 0; m < kModes; ++m)
             any = any || g_scratch[d][m].u[0];
         if (!any)
@@ -1019,6 +1227,7 @@ extern "C" void tvspec_release(void)
         for (int m = 0; m < kModes; ++m)
             free_scratch(g_scratch[d][m]);
         free_stage(g_stage[d]);
+        free_desc_stage(g_desc_stage[d]);
         if (g_stage[d].stream) {
             (void)hipStreamDestroy(g_stage[d].stream);
             g_stage[d].stream = nullptr;

@@ -35,6 +35,7 @@ TVSPEC_NSTATS = 4
 EXPORTS = (
     "tvspec_decompose",
     "tvspec_decompose_dev",
+    "tvspec_decompose_batch_dev",
     "tvspec_dyadic_edges",
     "tvspec_timing_enable",
     "tvspec_timing_read",
@@ -59,6 +60,9 @@ def _load():
     lib.tvspec_decompose.restype = i
     lib.tvspec_decompose_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, i, i, i, vp]
     lib.tvspec_decompose_dev.restype = i
+    lib.tvspec_decompose_batch_dev.argtypes = [vp, i, i, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, d, i, i, i,
+                                               vp]
+    lib.tvspec_decompose_batch_dev.restype = i
     lib.tvspec_dyadic_edges.argtypes = [i, i, vp]
     lib.tvspec_dyadic_edges.restype = i
     lib.tvspec_timing_enable.argtypes = [i]
@@ -187,4 +191,51 @@ def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, b
             out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
             out["stats"].data_ptr(), float(tau), 1 if warm_start else 0, prec,
             int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def tvspec_decompose_batch_dev(f: torch.Tensor, dt, K, inner_iters: int, band_edges,
+                               tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = False,
+                               precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
+                               stream: torch.cuda.Stream | None = None):
+    """Batched device entry point: f is a (B,C,H,W) float32 GPU tensor; dt and K
+    are length-B sequences, band_edges a length-B sequence of edge lists.
+
+    Returns a list of B dicts (views into shared output tensors) with bands
+    (n_bands_b,C,H,W), S (C,K_b), residual (C,H,W) and stats (4,)."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32 or f.dim() != 4:
+        raise TypeError("f must be a (B,C,H,W) float32 GPU tensor")
+    f = f.contiguous()
+    B, C, H, W = f.shape
+    dt_a = np.ascontiguousarray(np.asarray(dt, dtype=np.float64))
+    K_a = np.ascontiguousarray(np.asarray(K, dtype=np.int32))
+    if dt_a.shape != (B,) or K_a.shape != (B,) or len(band_edges) != B:
+        raise ValueError("dt, K and band_edges need one entry per image")
+    edges = [_edges_array(e) for e in band_edges]
+    nb = np.ascontiguousarray(np.array([e.size - 1 for e in edges], dtype=np.int32))
+    edges_cat = np.ascontiguousarray(np.concatenate(edges).astype(np.int32))
+    dev = f.device
+    bands = torch.empty((int(nb.sum()) * C * H * W,), dtype=torch.float64, device=dev)
+    S = torch.empty((int(C * K_a.sum()),), dtype=torch.float64, device=dev)
+    res = torch.empty((B, C, H, W), dtype=torch.float64, device=dev)
+    stats = torch.empty((B, TVSPEC_NSTATS), dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(_lib.tvspec_decompose_batch_dev(
+            f.data_ptr(), B, H, W, C, int(inner_iters), dt_a.ctypes.data, K_a.ctypes.data,
+            edges_cat.ctypes.data, nb.ctypes.data, bands.data_ptr(), S.data_ptr(), res.data_ptr(),
+            stats.data_ptr(), float(tau), 1 if warm_start else 0, PRECISIONS[precision],
+            int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
+    out = []
+    bo = so = 0
+    for b in range(B):
+        nbb, Kb = int(nb[b]), int(K_a[b])
+        out.append({
+            "bands": bands[bo:bo + nbb * C * H * W].view(nbb, C, H, W),
+            "S": S[so:so + C * Kb].view(C, Kb),
+            "residual": res[b],
+            "stats": stats[b],
+        })
+        bo += nbb * C * H * W
+        so += C * Kb
     return out

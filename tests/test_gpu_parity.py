@@ -275,3 +275,32 @@ def test_full_512_workload_parity(tv, orc):
     check_parity(gpu(tv, f, **kw), r)
     check_parity(gpu(tv, f, precision="f64", **kw), r)
     check_parity(gpu(tv, f, precision="f32", **kw), r, s_tol=TOL_S32, b_tol=TOL_BANDS_F32)
+
+
+def test_batch_equals_separate_calls(tv, orc):
+    """One batched launch sequence over images with different dt, K and band
+    edges gives each image's single-call result bit for bit, and matches the
+    oracle."""
+    imgs = np.stack([synth.shapes_image(synth.ShapeSpec(40, 72, 2, 5), seed=s) for s in range(5)])
+    dts = [0.005, 0.01, 0.002, 0.005, 0.02]
+    Ks = [12, 7, 20, 1, 9]
+    edges = [[0, 1, 2, 4, 12], [0, 7], [0, 1, 2, 4, 8, 16, 20], [0, 1], [0, 3, 9]]
+    iters = 21
+    ft = torch.from_numpy(imgs).to("cuda:0")
+    outs = tv.tvspec_decompose_batch_dev(ft, dts, Ks, iters, edges)
+    torch.cuda.synchronize()
+    for b in range(5):
+        one = gpu(tv, imgs[b], dts[b], Ks[b], iters, edges[b])
+        for k in ("bands", "S", "residual", "stats"):
+            assert np.array_equal(outs[b][k].cpu().numpy(), one[k]), (b, k)
+        r = orc.decompose(imgs[b], dts[b], Ks[b], iters, edges[b])
+        check_parity({k: v.cpu().numpy() for k, v in outs[b].items()}, r)
+
+
+def test_batch_validation(tv):
+    ft = torch.zeros((2, 1, 8, 8), device="cuda:0")
+    with pytest.raises(tv.TvspecError) as ei:
+        tv.tvspec_decompose_batch_dev(ft, [0.01, -1.0], [4, 4], 5, [[0, 4], [0, 4]])
+    assert ei.value.code == tv.TVSPEC_EINVAL and "image 1" in str(ei.value)
+    with pytest.raises(tv.TvspecError):
+        tv.tvspec_decompose_batch_dev(ft, [0.01, 0.01], [4, 4], 5, [[0, 4], [0, 2, 5]])
