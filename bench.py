@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_chambolle_tile_512x512_mixed_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "tvspec.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "engine.hip")
 
 
 def measured_traffic(precision, iters_per_launch):

@@ -45,6 +45,15 @@
 #ifndef TVSPEC_H
 #define TVSPEC_H
 
+#include <stddef.h>
+
+/* Symbols of the C ABI (the library is built with hidden visibility). */
+#if defined(__GNUC__) || defined(__clang__)
+#define TVSPEC_API __attribute__((visibility("default")))
+#else
+#define TVSPEC_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -91,7 +100,7 @@ extern "C" {
  * a NaN or infinity (checked on the host before any device work);
  * TVSPEC_ENOMEM; TVSPEC_EDEVICE.  Outputs are unspecified on error.
  */
-int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
+TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
                      const int *band_edges, int n_bands, double *bands, double *S,
                      double *residual);
 
@@ -129,7 +138,7 @@ int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int 
  * stats[2] instead of a return code.  Argument validation happens before any
  * device work.
  */
-int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
+TVSPEC_API int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
                          int inner_iters, const int *band_edges, int n_bands, double *bands,
                          double *S, double *residual, double *stats, double tau, int warm_start,
                          int precision, int iters_per_launch, void *stream);
@@ -157,7 +166,7 @@ int tvspec_decompose_dev(const float *f, int H, int W, int C, double dt, int K,
  * B < 1, B*C > 65535, or any image's invalid dt, K, n_bands or edges (the
  * message names the image), and as tvspec_decompose_dev otherwise.
  */
-int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int inner_iters,
+TVSPEC_API int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int inner_iters,
                                const double *dt, const int *K, const int *band_edges,
                                const int *n_bands, double *bands, double *S, double *residual,
                                double *stats, double tau, int warm_start, int precision,
@@ -170,7 +179,7 @@ int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int i
  * Errors: TVSPEC_EINVAL if K < 1, n_bands < 1, edges is NULL, or
  * 2^(B-2) >= K.
  */
-int tvspec_dyadic_edges(int K, int n_bands, int *edges);
+TVSPEC_API int tvspec_dyadic_edges(int K, int n_bands, int *edges);
 
 /*
  * Kernel timing for benchmarks.  While enabled (on = 1), the back-to-back
@@ -182,18 +191,18 @@ int tvspec_dyadic_edges(int K, int n_bands, int *edges);
  * Any pointer may be NULL.  Leave it off for throughput runs.
  * Errors: TVSPEC_EDEVICE (event creation, query or timing failed).
  */
-int tvspec_timing_enable(int on);
-int tvspec_timing_read(double *kernel_ms, long long *launches, long long *pixel_iters);
+TVSPEC_API int tvspec_timing_enable(int on);
+TVSPEC_API int tvspec_timing_read(double *kernel_ms, long long *launches, long long *pixel_iters);
 
 /* Text of the last error on the calling thread ("" if none). */
-const char *tvspec_last_error(void);
+TVSPEC_API const char *tvspec_last_error(void);
 
 /* Library version string. */
-const char *tvspec_version(void);
+TVSPEC_API const char *tvspec_version(void);
 
 /* Free every device buffer the library caches.  Must not overlap a call in
  * flight on any stream. */
-void tvspec_release(void);
+TVSPEC_API void tvspec_release(void);
 
 #ifdef __cplusplus
 }

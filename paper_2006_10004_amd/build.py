@@ -11,7 +11,8 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "tvspec.hip")
+SRCS = [os.path.join(PKG, "csrc", n) for n in ("engine.hip", "tvspec.hip")]
+SRC = SRCS[0]
 INC = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtvspec.so")
 
@@ -30,11 +31,13 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-mcode-object-version=5",
     "-Wall",
+    # only the C ABI (TVSPEC_API in the header) is exported
+    "-fvisibility=hidden",
 ]
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    cmd = [HIPCC] + FLAGS + (extra or []) + ["-I", INC, "-o", LIB + ".tmp", SRC]
+    cmd = [HIPCC] + FLAGS + (extra or []) + ["-I", INC, "-o", LIB + ".tmp"] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,7 +48,7 @@ def build(verbose: bool = False, extra=None) -> str:
     if msgs and (verbose or res.returncode != 0):
         print("\n".join(msgs), file=sys.stderr)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed building %s" % SRC)
+        raise RuntimeError("hipcc failed building %s" % LIB)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,0 +1,821 @@
+// tvspec engine: kernels and launchers of the spectral TV decomposition on
+// gfx950, over a table of image slots (see engine.h).
+//
+// Method: Grossmann, Korolev, Gilboa, Schoenlieb, arXiv 2006.10004.
+//   Sec. 2.2 Eq. (8)   one implicit Euler step of the TV flow Eq. (1) is a ROF
+//                      problem; it is solved here by Chambolle's dual
+//                      projection iteration (the solver Sec. 4.3 names);
+//   Sec. 2.1 Eq. (3)   phi(t_k) = t_k u_tt(t_k) by the central second
+//                      difference, S(t_k) = ||phi(t_k)||_1, band integrals of
+//                      Eq. (7) and the residual of Eq. (5).
+//
+// Device work per slot (one C x H x W image, channels independent):
+//   k_init           u_0 = f (float64), G = grad(f)/dt for the first solve,
+//                    p = 0, bands = 0, count of non-finite inputs;
+//   k_chambolle_tile the hot loop.  Each launch runs `iters` (<= TB) Jacobi
+//                    iterations of Chambolle's fixed point on a 32x32 output
+//                    tile whose (32+2TB)^2 neighbourhood is staged once; the
+//                    dual field stays in registers, only neighbour values
+//                    cross lanes through LDS.  Tiles are mapped to workgroups
+//                    so that each XCD works on one horizontal band of the
+//                    image (neighbouring halos then hit the same L2);
+//   k_flow_step      one launch per ROF solve, fused: div p, u_{s+1} =
+//                    u_s - dt div p, D_s = dt div p, phi_s dt = s (D_{s-1} -
+//                    D_s) added to its band, a per-block partial of sum |D_{s-1}
+//                    - D_s| for S(t_s), the residual at s = K, and grad(g)/dt
+//                    of the next solve.  u_{s-1} and u_{s+1} never exist as
+//                    planes beside u_s;
+//   k_advance        moves every active slot to its next step;
+//   k_check          per-block partials of the reconstruction error and of
+//                    the mean of u_{K+1} and f;
+//   k_reduce_s       S(t_k) from the step partials, one block per (k, c);
+//   k_report         the report (reductions in a fixed order, so results are
+//                    bit-reproducible run to run).
+//
+// Precision modes of the inner iteration.  S is the type of the dual field
+// and of the update arithmetic, M the type G is stored in:
+//   F32    S = float,  M = float   (IEEE-rounded float32 except the
+//          hardware square root and reciprocal estimates)
+//   F64    S = double, M = double  (IEEE float64 throughout)
+//   MIXED  S = double, M = float.  float64 arithmetic, but |a| and the
+//          reciprocal come from the float32 hardware estimates refined by one
+//          float64 Newton step, and G is stored in float32.  On gfx950, with
+//          packed float32 math off, float64 add and fma issue at the float32
+//          rate; what makes float64 dear is its square root and division
+//          sequences, which this avoids.  Float32 is not enough for long
+//          flows: with dt = 0.002 and 200 steps the spectral sums weight
+//          differences of the flow by up to 200, and the float32 rounding of
+//          div p (a cancelling difference of O(1) values) and of the update's
+//          nonlinear factor then moves the bands by ~4e-4.
+// The flow state u, D, phi, the bands, S and the checks are float64 always.
+//
+// Arithmetic contract: every kernel variant (any temporal blocking factor)
+// applies the same per-pixel operations in the same order, so results do not
+// depend on the launch configuration or on which other slots share a table.
+// Build with -ffp-contract=off; fused multiply-adds are written explicitly.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "engine.h"
+
+namespace tvspec {
+
+thread_local std::string g_last_error;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// scalar operations of the Chambolle update
+
+template <typename M> struct Arith;
+
+template <> struct Arith<float> {
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    // one reciprocal shared by both components
+    static __device__ __forceinline__ float inv_(float d) { return __builtin_amdgcn_rcpf(d); }
+};
+
+template <> struct Arith<double> {
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double inv_(double d) { return 1.0 / d; }
+};
+
+// One Chambolle update of a pixel's dual vector from the gradient a of
+// div p - g/dt:  p <- (p + tau a) / (1 + tau |a|).
+// |a| is formed as ax*ax + ay*ay (not a fused multiply-add) so that the
+// update is symmetric in x and y, like the method.
+template <typename S, typename M>
+__device__ __forceinline__ void chambolle_update(S &px, S &py, S ax, S ay, S tau)
+{
+    if constexpr (std::is_same<S, M>::value) {
+        using A = Arith<S>;
+        const S nrm = A::sqrt_(ax * ax + ay * ay);
+        const S r = A::inv_(A::fma_(tau, nrm, S(1)));
+        px = A::fma_(tau, ax, px) * r;
+        py = A::fma_(tau, ay, py) * r;
+    } else {
+        // float64 update in increment form, p += tau (a - |a| p) / (1 + tau |a|),
+        // with |a| and the reciprocal from the float32 hardware estimates
+        // (v_rsq_f32, v_rcp_f32) refined by one Newton step in float64
+        // (relative error ~1e-14; the float64 square root and division
+        // sequences cost several times more).  Below |a| = 1e-15 the
+        // estimate's argument would leave the float32 normal range, and |a| is
+        // taken as 0: the increment then differs by at most tau |a| |p|, far
+        // below the rounding of p.
+        const S x = ax * ax + ay * ay;
+        S y = (S)__builtin_amdgcn_rsqf((float)x);
+        y = __builtin_fma(S(0.5) * y, __builtin_fma(-(x * y), y, S(1)), y);
+        const S nrm = x > S(1e-30) ? x * y : S(0);
+        const S den = __builtin_fma(tau, nrm, S(1));
+        S r = (S)__builtin_amdgcn_rcpf((float)den);
+        r = __builtin_fma(r, __builtin_fma(-den, r, S(1)), r);
+        const S tr = tau * r;
+        px += tr * __builtin_fma(-nrm, px, ax);
+        py += tr * __builtin_fma(-nrm, py, ay);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reductions (wave64, fixed order)
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+constexpr int kThreads = 256;
+
+// Block of 256 threads (4 waves).  Every thread returns the block result.
+__device__ __forceinline__ double block_sum256(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[wid] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__device__ __forceinline__ double block_max256(double v, double *sh)
+{
+    v = wave_max(v);
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[wid] = v;
+    __syncthreads();
+    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+// u_0 = f, G = grad f / dt, p = 0 (both buffers), bands = 0, for slot
+// first + blockIdx.y; counts non-finite inputs; starts the slot at step 0.
+template <typename S, typename M>
+__global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots, int first, int H, int W, int C)
+{
+    SlotDesc &sd = slots[first + blockIdx.y];
+    const int plane = H * W;
+    const size_t n = (size_t)C * (size_t)plane;
+    const double dt = sd.dt;
+    const float *__restrict__ f = sd.f;
+    S *__restrict__ p0 = (S *)sd.px[0];
+    S *__restrict__ p1 = (S *)sd.px[1];
+    S *__restrict__ p2 = (S *)sd.py[0];
+    S *__restrict__ p3 = (S *)sd.py[1];
+    M *__restrict__ gx = (M *)sd.gx;
+    M *__restrict__ gy = (M *)sd.gy;
+    double *__restrict__ u = sd.u[0];
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    for (size_t q = (size_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += stride) {
+        const int qq = (int)(q % (size_t)plane);
+        const int i = qq / W;
+        const int j = qq - i * W;
+        const float v = f[q];
+        if (!isfinite(v))
+            atomicAdd(sd.nonfinite, 1u);
+        u[q] = (double)v;
+        gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
+        gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
+        p0[q] = S(0);
+        p1[q] = S(0);
+        p2[q] = S(0);
+        p3[q] = S(0);
+        for (int k = 0; k < sd.nbands; ++k)
+            sd.bands[(size_t)k * n + q] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sd.k_cur = 0;
+        sd.active = 1;
+    }
+}
+
+// Temporally blocked Chambolle iterations.
+//
+// Chambolle's step needs a = grad(div p - g/dt).  It is evaluated as
+//     a = grad(div p) - G,   G = grad(g)/dt,
+// with G formed in float64 from the float64 flow state and stored in type M.
+// This is the same quantity; the order matters in float32: g/dt is large
+// (|g| <= 1, dt ~ 1e-3) and differencing two rounded values of it would bury
+// the small gradients of flat regions, whereas G carries only the relative
+// rounding of the gradient itself.
+//
+// Grid: (number of BX x BY output tiles, slots * C); 1024 threads, so that every
+// SIMD of the CU has four waves to interleave (the per-pixel chain of LDS
+// reads, square root and reciprocal is long and a tile holds few pixels).
+// The workgroup stages the (BX+2TB) x (BY+2TB) region around its tile: the
+// dual field and G of every region pixel live in registers of the thread
+// that owns the pixel for all `iters` iterations; LDS only carries the
+// values a neighbour needs (px of the left pixel and py of the upper one for
+// div p, div p of the right and lower pixels for its gradient).  The LDS
+// planes carry a one-pixel ring that is never written, so neighbour reads
+// need no tests.  One iteration on every region pixel:
+//     d   = (px - px_left) + (py - py_up)                      (div p)
+//     a   = ((d_right - d) - Gx, (d_down - d) - Gy), zero on the last
+//           column / row and outside the image
+//     p  <- (p + tau a) / (1 + tau |a|)
+// Pixels outside the image start with p = 0 and a = 0, so they keep p = 0;
+// that realises the Neumann divergence (p_x = 0 on the last column and
+// p_y = 0 on the last row is preserved by the update because a_x, a_y vanish
+// there).  With zero_in set (first launch of a cold-started solve) the
+// incoming dual field is taken as zero instead of being read.  The dual field
+// is read from buffer `cur` of the slot and written to buffer 1 - cur.
+// Channel planes of slots whose flow is complete (inactive) are skipped.  A region
+// pixel at distance e from the region edge is exact while the iteration
+// count is <= e, so after iters <= TB iterations the BX x BY centre is exact
+// and is written.
+constexpr int kTileThreads = 1024;
+
+template <typename S, typename M, int BX, int BY, int TB>
+__global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc *__restrict__ slots, int cur, int H,
+                                                                int W, int C, int ntx, int ntiles, S tau, int iters,
+                                                                int zero_in)
+{
+    const int slot = blockIdx.y / C;
+    const int chan = blockIdx.y - slot * C;
+    const SlotDesc &sd = slots[slot];
+    if (!sd.active)
+        return;
+    constexpr int RX = BX + 2 * TB;
+    constexpr int RY = BY + 2 * TB;
+    constexpr int RN = RX * RY;
+    constexpr int LX = RX + 2;            // LDS row pitch: region + zero ring
+    constexpr int LN = LX * (RY + 2);
+    constexpr int PPT = (RN + kTileThreads - 1) / kTileThreads;
+    __shared__ S s_px[LN];
+    __shared__ S s_py[LN];
+    __shared__ S s_d[LN];
+
+    const size_t plane = (size_t)H * (size_t)W;
+    const size_t coff = (size_t)chan * plane;
+    const S *__restrict__ pxi = (const S *)sd.px[cur] + coff;
+    const S *__restrict__ pyi = (const S *)sd.py[cur] + coff;
+    const M *__restrict__ gxi = (const M *)sd.gx + coff;
+    const M *__restrict__ gyi = (const M *)sd.gy + coff;
+    S *__restrict__ pxo = (S *)sd.px[1 - cur] + coff;
+    S *__restrict__ pyo = (S *)sd.py[1 - cur] + coff;
+
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
+    // so give XCD x the x-th contiguous run of row-major tiles.
+    const int b = blockIdx.x;
+    const int L = ((ntiles & 7) == 0) ? (b & 7) * (ntiles >> 3) + (b >> 3) : b;
+    const int ty = L / ntx;
+    const int tx = L - ty * ntx;
+    const int oy = ty * BY - TB;
+    const int ox = tx * BX - TB;
+
+    // zero ring (read by the outermost region pixels only)
+    for (int e = threadIdx.x; e < 2 * LX + 2 * RY; e += kTileThreads) {
+        int li;
+        if (e < LX)
+            li = e;                              // top row
+        else if (e < 2 * LX)
+            li = (RY + 1) * LX + (e - LX);       // bottom row
+        else if (e < 2 * LX + RY)
+            li = (e - 2 * LX + 1) * LX;          // left column
+        else
+            li = (e - 2 * LX - RY + 1) * LX + LX - 1; // right column
+        s_px[li] = S(0);
+        s_py[li] = S(0);
+        s_d[li] = S(0);
+    }
+
+    S px[PPT], py[PPT], d[PPT], gx[PPT], gy[PPT];
+    int li[PPT];     // LDS index of the pixel
+    S mx[PPT];       // 1 where a_x is live (inside the image, not its last column), else 0
+    S my[PPT];       // 1 where a_y is live (inside the image, not its last row), else 0
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int idx = threadIdx.x + m * kTileThreads;
+        S vx = S(0), vy = S(0);
+        M vgx = M(0), vgy = M(0);
+        bool ax_live = false, ay_live = false;
+        int l = 0;
+        if (idx < RN) {
+            const int ri = idx / RX;
+            const int rj = idx - ri * RX;
+            const int gi = oy + ri;
+            const int gj = ox + rj;
+            l = (ri + 1) * LX + (rj + 1);
+            if (gi >= 0 && gi < H && gj >= 0 && gj < W) {
+                const size_t q = (size_t)gi * W + gj;
+                if (!zero_in) {
+                    vx = pxi[q];
+                    vy = pyi[q];
+                }
+                vgx = gxi[q];
+                vgy = gyi[q];
+                ax_live = gj < W - 1;
+                ay_live = gi < H - 1;
+            }
+            s_px[l] = vx;
+            s_py[l] = vy;
+        }
+        li[m] = l;
+        px[m] = vx;
+        py[m] = vy;
+        gx[m] = (S)vgx;
+        gy[m] = (S)vgy;
+        d[m] = S(0);
+        mx[m] = ax_live ? S(1) : S(0);
+        my[m] = ay_live ? S(1) : S(0);
+    }
+    __syncthreads();
+
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
+                const int l = li[m];
+                const S dv = (px[m] - s_px[l - 1]) + (py[m] - s_py[l - LX]);
+                d[m] = dv;
+                s_d[l] = dv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
+                const int l = li[m];
+                // unconditional LDS reads; the boundary masks multiply (a
+                // select around the reads compiles to branches that expose
+                // the LDS latency of every pixel)
+                const S dr = s_d[l + 1];
+                const S dd = s_d[l + LX];
+                const S ax = ((dr - d[m]) - gx[m]) * mx[m];
+                const S ay = ((dd - d[m]) - gy[m]) * my[m];
+                chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
+                s_px[l] = px[m];
+                s_py[l] = py[m];
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int idx = threadIdx.x + m * kTileThreads;
+        if (idx < RN) {
+            const int ri = idx / RX;
+            const int rj = idx - ri * RX;
+            const int gi = oy + ri;
+            const int gj = ox + rj;
+            if (ri >= TB && ri < TB + BY && rj >= TB && rj < TB + BX && gi < H && gj < W) {
+                const size_t q = (size_t)gi * W + gj;
+                pxo[q] = px[m];
+                pyo[q] = py[m];
+            }
+        }
+    }
+}
+
+// div p at pixel q = (i, j) of one channel plane, in float64 from the stored
+// dual field (zero outside the image).
+template <typename S>
+__device__ __forceinline__ double div_p(const S *__restrict__ px, const S *__restrict__ py, int q, int i, int j,
+                                        int W)
+{
+    const double pxl = (j > 0) ? (double)px[q - 1] : 0.0;
+    const double pyu = (i > 0) ? (double)py[q - W] : 0.0;
+    return ((double)px[q] - pxl) + ((double)py[q] - pyu);
+}
+
+// Outer step k = k_cur of every active slot, fused with the spectral
+// transform.  Grid: (nblk, slots * C), nblk fixed per image size so partial
+// sums are reproducible.  The final dual field of the solve is in buffer cur.
+//   D_k     = dt div p                     (u_k - u_{k+1})
+//   u_{k+1} = u_k - D_k                    (u[(k+1) % 2])
+//   k >= 1: phi_k dt = k (D_{k-1} - D_k)   added to the band holding k
+//           spart  <- block sum of |D_{k-1} - D_k|   (S(t_k) = k/dt * total)
+//   k == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t)
+//   G       = grad(u_{k+1}) / dt           (data term of the next solve; the
+//             right and lower neighbours' u_{k+1} are recomputed here with
+//             the same operations their own threads use, so they match bit
+//             for bit)
+template <typename S, typename M>
+__global__ __launch_bounds__(kThreads) void k_flow_step(const SlotDesc *__restrict__ slots, int cur, int H, int W,
+                                                        int C)
+{
+    __shared__ double sh[4];
+    const int slot = blockIdx.y / C;
+    const int c = blockIdx.y - slot * C;
+    const SlotDesc &sd = slots[slot];
+    if (!sd.active)
+        return;
+    const int k = sd.k_cur;
+    const int K = sd.K;
+    const double dt = sd.dt;
+    const int plane = H * W;
+    const size_t coff = (size_t)c * (size_t)plane;
+    const S *__restrict__ px = (const S *)sd.px[cur] + coff;
+    const S *__restrict__ py = (const S *)sd.py[cur] + coff;
+    const double *__restrict__ uin = sd.u[k & 1] + coff;
+    double *__restrict__ uout = sd.u[(k + 1) & 1] + coff;
+    double *__restrict__ dprev = sd.dprev + coff;
+    M *__restrict__ gx = (M *)sd.gx + coff;
+    M *__restrict__ gy = (M *)sd.gy + coff;
+    double *__restrict__ resid = sd.res + coff;
+    double *__restrict__ band = nullptr;
+    if (k >= 1)
+        band = sd.bands + ((size_t)sd.band_rows[k] * C + c) * (size_t)plane;
+    const double kd = (double)k;
+    double acc = 0.0;
+    for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
+        const int i = q / W;
+        const int j = q - i * W;
+        const double D = dt * div_p(px, py, q, i, j, W);
+        const double uo = uin[q];
+        const double un = uo - D;
+        if (k >= 1) {
+            const double dl = dprev[q] - D;
+            band[q] += kd * dl;
+            acc += fabs(dl);
+        }
+        if (k == K)
+            resid[q] = uo + (double)K * D;
+        uout[q] = un;
+        dprev[q] = D;
+        if (j < W - 1) {
+            const double unr = uin[q + 1] - dt * div_p(px, py, q + 1, i, j + 1, W);
+            gx[q] = (M)((unr - un) / dt);
+        } else {
+            gx[q] = M(0);
+        }
+        if (i < H - 1) {
+            const double und = uin[q + W] - dt * div_p(px, py, q + W, i + 1, j, W);
+            gy[q] = (M)((und - un) / dt);
+        } else {
+            gy[q] = M(0);
+        }
+    }
+    if (k >= 1) {
+        acc = block_sum256(acc, sh);
+        if (threadIdx.x == 0)
+            sd.spart[((size_t)(k - 1) * C + c) * gridDim.x + blockIdx.x] = acc;
+    }
+}
+
+// Every active slot moves to its next step; a slot that has run step K
+// becomes inactive (its k_cur ends at K + 1).
+__global__ __launch_bounds__(kThreads) void k_advance(SlotDesc *__restrict__ slots, int nslots)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= nslots || !slots[i].active)
+        return;
+    if (slots[i].k_cur == slots[i].K)
+        slots[i].active = 0;
+    slots[i].k_cur += 1;
+}
+
+// Per-block partials of: max |f - sum_j b_j - r|, sum u_{K+1}, sum f, for
+// completed slots first, first + 1, ...  Grid: (nblk, count * C).  u_{K+1}
+// is in u[(K + 1) % 2].
+__global__ __launch_bounds__(kThreads) void k_check(const SlotDesc *__restrict__ slots, int first, int plane, int C)
+{
+    __shared__ double sh[4];
+    const int rel = blockIdx.y / C;
+    const SlotDesc &sd = slots[first + rel];
+    const int c = blockIdx.y - rel * C;
+    const size_t coff = (size_t)c * (size_t)plane;
+    const double *__restrict__ u = sd.u[(sd.K + 1) & 1] + coff;
+    const double *__restrict__ b0 = sd.bands + coff;
+    const size_t bstride = (size_t)C * (size_t)plane;
+    double emax = 0.0, su = 0.0, sf = 0.0;
+    for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < sd.nbands; ++j)
+            acc += b0[(size_t)j * bstride + q];
+        const double fv = (double)sd.f[coff + q];
+        emax = fmax(emax, fabs(fv - acc - sd.res[coff + q]));
+        su += u[q];
+        sf += fv;
+    }
+    emax = block_max256(emax, sh);
+    su = block_sum256(su, sh);
+    sf = block_sum256(sf, sh);
+    if (threadIdx.x == 0) {
+        double *o = sd.rpart + ((size_t)c * gridDim.x + blockIdx.x) * 3;
+        o[0] = emax;
+        o[1] = su;
+        o[2] = sf;
+    }
+}
+
+// S of completed slots first, first + 1, ...: S[c][k-1] = k/dt * (sum of
+// the step partials of sample k, channel c); one block per (k, slot, c), each
+// thread summing a fixed stride of partials, then the block sum in a fixed
+// order.  Grid: (max K, count * C); blocks beyond a slot's K exit.
+__global__ __launch_bounds__(kThreads) void k_reduce_s(const SlotDesc *__restrict__ slots, int first, int C,
+                                                       int nblk)
+{
+    __shared__ double sh[4];
+    const int rel = blockIdx.y / C;
+    const SlotDesc &sd = slots[first + rel];
+    const int k = blockIdx.x + 1;
+    const int c = blockIdx.y - rel * C;
+    if (k > sd.K)
+        return;
+    const double *p = sd.spart + ((size_t)(k - 1) * C + c) * nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+        s += p[b];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0)
+        sd.S[(size_t)c * sd.K + (k - 1)] = s * ((double)k / sd.dt);
+}
+
+// The report of completed slot first + blockIdx.x from its check partials
+// (fixed reduction order); clears the slot's non-finite counter.
+__global__ __launch_bounds__(kThreads) void k_report(const SlotDesc *__restrict__ slots, int first, int C,
+                                                     int nblk_chk, int plane)
+{
+    __shared__ double sh[4];
+    const SlotDesc &sd = slots[first + blockIdx.x];
+    double emax = 0.0, drift = 0.0;
+    for (int c = 0; c < C; ++c) {
+        double e = 0.0, su = 0.0, sf = 0.0;
+        for (int b = threadIdx.x; b < nblk_chk; b += kThreads) {
+            const double *o = sd.rpart + ((size_t)c * nblk_chk + b) * 3;
+            e = fmax(e, o[0]);
+            su += o[1];
+            sf += o[2];
+        }
+        e = block_max256(e, sh);
+        su = block_sum256(su, sh);
+        sf = block_sum256(sf, sh);
+        emax = fmax(emax, e);
+        drift = fmax(drift, fabs(su / (double)plane - sf / (double)plane));
+    }
+    if (threadIdx.x == 0) {
+        sd.stats[0] = emax;
+        sd.stats[1] = drift;
+        sd.stats[2] = (double)(*sd.nonfinite);
+        sd.stats[3] = 0.0;
+        *sd.nonfinite = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch configuration
+
+constexpr int kTileX = 32;
+constexpr int kTileY = 32;
+
+int blocks_for(size_t n, int cap)
+{
+    size_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > (size_t)cap) b = cap;
+    return (int)b;
+}
+
+template <typename S, typename M>
+using TileKernel = void (*)(const SlotDesc *, int, int, int, int, int, int, S, int, int);
+
+// Largest temporal blocking factor compiled for a mode (LDS and registers of
+// the (32+2TB)^2 region, which are sized by the dual-field type S).
+template <typename S> constexpr int max_tb() { return std::is_same<S, float>::value ? 16 : 8; }
+
+// Smallest compiled halo width >= t.
+template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
+{
+    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1>; }
+    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2>; }
+    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4>; }
+    if constexpr (max_tb<S>() >= 16) {
+        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16>; }
+    }
+    *tb = 8;
+    return k_chambolle_tile<S, M, kTileX, kTileY, 8>;
+}
+
+// ---------------------------------------------------------------------------
+// benchmark timing of the tile kernel: one event pair per engine_step
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev; // start, stop, start, stop, ...
+    size_t used = 0;            // pairs recorded and not yet read
+    double ms = 0.0;            // time of pairs already read
+    long long launches = 0;
+    long long pixel_iters = 0;
+};
+Timing g_timing;
+constexpr size_t kMaxTimingPairs = 1 << 15;
+
+int timing_drain()
+{
+    for (size_t i = 0; i < g_timing.used; ++i) {
+        HIP_TRY(hipEventSynchronize(g_timing.ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]));
+        g_timing.ms += ms;
+    }
+    g_timing.used = 0;
+    return TVSPEC_OK;
+}
+
+int timing_pair(hipEvent_t *a, hipEvent_t *b)
+{
+    if (g_timing.used == kMaxTimingPairs)
+        TVSPEC_TRY(timing_drain());
+    while (g_timing.ev.size() < 2 * (g_timing.used + 1)) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        g_timing.ev.push_back(e);
+    }
+    *a = g_timing.ev[2 * g_timing.used];
+    *b = g_timing.ev[2 * g_timing.used + 1];
+    ++g_timing.used;
+    return TVSPEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launchers per mode
+
+template <typename S, typename M> int init_impl(const StepConfig &cfg, SlotDesc *d_slots, int first, int count,
+                                                hipStream_t st)
+{
+    const size_t n = (size_t)cfg.C * cfg.H * cfg.W;
+    hipLaunchKernelGGL((k_init<S, M>), dim3(blocks_for(n, 1024), count), dim3(kThreads), 0, st, d_slots, first,
+                       cfg.H, cfg.W, cfg.C);
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc *d_slots, int nslots, int *parity,
+                                                hipStream_t st, long long live_planes)
+{
+    const int plane = cfg.H * cfg.W;
+    int tb = 0;
+    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : 8;
+    TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
+    const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
+    const int ntx = (cfg.W + kTileX - 1) / kTileX;
+    const int nty = (cfg.H + kTileY - 1) / kTileY;
+    const int ntiles = ntx * nty;
+    int cur = *parity;
+
+    // timing: one event pair around the back-to-back Chambolle launches of
+    // this solve (events between launches would perturb them)
+    const bool timed = cfg.timed && g_timing.on;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        TVSPEC_TRY(timing_pair(&e0, &e1));
+        HIP_TRY(hipEventRecord(e0, st));
+    }
+    for (int done = 0; done < cfg.iters;) {
+        // cold start: the first launch of a solve starts from p = 0
+        const int zero_in = (!cfg.warm && done == 0) ? 1 : 0;
+        const int it = (cfg.iters - done) < per_launch ? (cfg.iters - done) : per_launch;
+        hipLaunchKernelGGL(kt, dim3(ntiles, nslots * cfg.C), dim3(kTileThreads), 0, st, d_slots, cur, cfg.H, cfg.W,
+                           cfg.C, ntx, ntiles, (S)cfg.tau, it, zero_in);
+        if (timed) {
+            ++g_timing.launches;
+            g_timing.pixel_iters += live_planes * plane * it;
+        }
+        cur = 1 - cur;
+        done += it;
+    }
+    if (timed)
+        HIP_TRY(hipEventRecord(e1, st));
+    hipLaunchKernelGGL((k_flow_step<S, M>), dim3(plane_blocks(plane), nslots * cfg.C), dim3(kThreads), 0, st,
+                       d_slots, cur, cfg.H, cfg.W, cfg.C);
+    hipLaunchKernelGGL(k_advance, dim3((nslots + kThreads - 1) / kThreads), dim3(kThreads), 0, st, d_slots, nslots);
+    HIP_TRY(hipGetLastError());
+    *parity = cur;
+    return TVSPEC_OK;
+}
+
+} // namespace
+
+size_t state_elem(int precision) { return precision == TVSPEC_PRECISION_F32 ? 4 : 8; }
+size_t g_elem(int precision) { return precision == TVSPEC_PRECISION_F64 ? 8 : 4; }
+
+int plane_blocks(int plane) { return blocks_for((size_t)plane, 1024); }
+
+size_t slot_scratch_bytes(int precision, int H, int W, int C, int K)
+{
+    const size_t n = (size_t)C * H * W;
+    const size_t nblk = (size_t)plane_blocks(H * W);
+    return 4 * align256(n * state_elem(precision))     // px[2], py[2]
+           + 2 * align256(n * g_elem(precision))        // gx, gy
+           + 3 * align256(n * sizeof(double))           // u[2], dprev
+           + align256((size_t)K * C * nblk * sizeof(double)) // spart
+           + align256((size_t)C * nblk * 3 * sizeof(double)); // rpart
+}
+
+void slot_carve(SlotDesc &d, char *base, int precision, int H, int W, int C, int K)
+{
+    const size_t n = (size_t)C * H * W;
+    const size_t nblk = (size_t)plane_blocks(H * W);
+    char *p = base;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    d.px[0] = take(n * state_elem(precision));
+    d.px[1] = take(n * state_elem(precision));
+    d.py[0] = take(n * state_elem(precision));
+    d.py[1] = take(n * state_elem(precision));
+    d.gx = take(n * g_elem(precision));
+    d.gy = take(n * g_elem(precision));
+    d.u[0] = (double *)take(n * sizeof(double));
+    d.u[1] = (double *)take(n * sizeof(double));
+    d.dprev = (double *)take(n * sizeof(double));
+    d.spart = (double *)take((size_t)K * C * nblk * sizeof(double));
+    d.rpart = (double *)take((size_t)C * nblk * 3 * sizeof(double));
+    d.K = K;
+}
+
+void band_rows_of(const int *edges, int nbands, int *rows)
+{
+    rows[0] = 0; // sample 0 carries no phi
+    for (int j = 0; j < nbands; ++j)
+        for (int k = edges[j] + 1; k <= edges[j + 1]; ++k)
+            rows[k] = j;
+}
+
+int tile_launches_per_step(const StepConfig &cfg)
+{
+    int tb = 0;
+    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : 8;
+    if (cfg.precision == TVSPEC_PRECISION_F32)
+        (void)tile_kernel<float, float>(want, &tb);
+    else
+        (void)tile_kernel<double, double>(want, &tb);
+    const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
+    return (cfg.iters + per_launch - 1) / per_launch;
+}
+
+int engine_init(const StepConfig &cfg, SlotDesc *d_slots, int first, int count, hipStream_t st)
+{
+    switch (cfg.precision) {
+    case TVSPEC_PRECISION_F32: return init_impl<float, float>(cfg, d_slots, first, count, st);
+    case TVSPEC_PRECISION_F64: return init_impl<double, double>(cfg, d_slots, first, count, st);
+    default: return init_impl<double, float>(cfg, d_slots, first, count, st);
+    }
+}
+
+int engine_step(const StepConfig &cfg, SlotDesc *d_slots, int nslots, int *parity, hipStream_t st,
+                long long live_planes)
+{
+    switch (cfg.precision) {
+    case TVSPEC_PRECISION_F32: return step_impl<float, float>(cfg, d_slots, nslots, parity, st, live_planes);
+    case TVSPEC_PRECISION_F64: return step_impl<double, double>(cfg, d_slots, nslots, parity, st, live_planes);
+    default: return step_impl<double, float>(cfg, d_slots, nslots, parity, st, live_planes);
+    }
+}
+
+int engine_finalize(const StepConfig &cfg, SlotDesc *d_slots, int first, int count, int Kmax, hipStream_t st)
+{
+    const int plane = cfg.H * cfg.W;
+    const int nblk = plane_blocks(plane);
+    hipLaunchKernelGGL(k_check, dim3(nblk, count * cfg.C), dim3(kThreads), 0, st, d_slots, first, plane, cfg.C);
+    hipLaunchKernelGGL(k_reduce_s, dim3(Kmax, count * cfg.C), dim3(kThreads), 0, st, d_slots, first, cfg.C, nblk);
+    hipLaunchKernelGGL(k_report, dim3(count), dim3(kThreads), 0, st, d_slots, first, cfg.C, nblk, plane);
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+int timing_enable(int on)
+{
+    g_timing.on = on != 0;
+    return TVSPEC_OK;
+}
+
+int timing_read(double *kernel_ms, long long *launches, long long *pixel_iters)
+{
+    TVSPEC_TRY(timing_drain());
+    if (kernel_ms) *kernel_ms = g_timing.ms;
+    if (launches) *launches = g_timing.launches;
+    if (pixel_iters) *pixel_iters = g_timing.pixel_iters;
+    g_timing.ms = 0.0;
+    g_timing.launches = 0;
+    g_timing.pixel_iters = 0;
+    return TVSPEC_OK;
+}
+
+} // namespace tvspec
