@@ -64,6 +64,8 @@ extern "C" {
 #define TVSPEC_ENUMERIC (-2) /* non-finite input value (host entry point only) */
 #define TVSPEC_ENOMEM (-3)   /* device or host allocation failed */
 #define TVSPEC_EDEVICE (-4)  /* HIP runtime error; tvspec_last_error() has the text */
+#define TVSPEC_EBUSY (-5)    /* request can never fit the server's memory budget */
+#define TVSPEC_PENDING 1     /* tvspec_poll: the request is not complete yet */
 
 /* Precision of the inner Chambolle iteration:
  *   F32    float32 dual field and arithmetic (fastest; on long flows its
@@ -171,6 +173,106 @@ TVSPEC_API int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, i
                                const int *n_bands, double *bands, double *S, double *residual,
                                double *stats, double tau, int warm_start, int precision,
                                int iters_per_launch, void *stream);
+
+/*
+ * Decomposition server: continuous batching of requests of mixed sizes on
+ * one device (the spectral transform of Sec. 2.1 over the flow of Sec. 2.2,
+ * as tvspec_decompose_dev, for a stream of images).
+ *
+ * A server owns a worker thread, one pool of device memory of budget_bytes
+ * for the requests' working state, and one stream per size bucket (requests
+ * with equal H, W, C and inner_iters).  A submitted request waits in a FIFO
+ * queue until its working state fits in the pool and its bucket has a free
+ * slot; it is then admitted at the bucket's next step boundary and advances
+ * one ROF solve per bucket step alongside the bucket's other requests.
+ * Buckets step concurrently on their streams; requests leave as they
+ * complete, which frees their memory and slot for the next admission.
+ * Every request's results equal those of tvspec_decompose_dev with the
+ * server's options, bit for bit, whatever else is in flight.
+ *
+ * Working state per request (what admission charges against the budget):
+ * about C*H*W*(2*4*s + 2*g + 24) bytes + C*K*8*ceil(H*W/256) for the
+ * partial sums of S, with s = 4 (F32) or 8 bytes per dual-field element and
+ * g = 4 (F32, MIXED) or 8 (F64) per stored data-term element.
+ *
+ *   budget_bytes      size of the pool (allocated at creation)
+ *   tau, warm_start, precision
+ *                     as tvspec_decompose_dev, for every request
+ *   iters_per_launch  as tvspec_decompose_dev; 0 = picked per bucket by the
+ *                     server's autotuner, which times the bucket's first
+ *                     steps with each candidate temporal blocking factor
+ *                     (results do not depend on the choice)
+ *   use_graphs        1: each bucket's step (its tile-kernel launches, the
+ *                     fused outer step and the slot advance) is captured
+ *                     once in a hipGraph and replayed; 0: launched directly
+ *
+ * The server is bound to the device current at creation.  Errors:
+ * TVSPEC_EINVAL (bad option, budget_bytes < 1 MiB, out NULL), TVSPEC_ENOMEM,
+ * TVSPEC_EDEVICE.
+ */
+typedef struct tvspec_server tvspec_server;
+
+typedef struct tvspec_request {
+    const float *f;         /* device [C][H][W]; must hold its values when submitted */
+    int H, W, C;
+    double dt;
+    int K;
+    int inner_iters;
+    const int *band_edges;  /* host, n_bands + 1 entries; copied by tvspec_submit */
+    int n_bands;
+    double *bands;          /* device outputs, layouts as tvspec_decompose_dev */
+    double *S;
+    double *residual;
+    double *stats;          /* device, TVSPEC_NSTATS doubles */
+} tvspec_request;
+
+typedef struct tvspec_result {
+    double queue_ms;        /* submission to admission */
+    double latency_ms;      /* submission to completion of every output */
+} tvspec_result;
+
+typedef struct tvspec_server_stats {
+    unsigned long long submitted, admitted, completed;
+    unsigned long long steps;        /* bucket steps enqueued */
+    unsigned long long graph_builds; /* step graphs captured */
+    int buckets;
+    int max_in_flight;               /* most requests admitted at once */
+    size_t budget_bytes, used_bytes, peak_bytes;
+} tvspec_server_stats;
+
+TVSPEC_API int tvspec_server_create(size_t budget_bytes, double tau, int warm_start, int precision,
+                                    int iters_per_launch, int use_graphs, tvspec_server **out);
+
+/*
+ * Queue one request.  The request's device buffers are the caller's and must
+ * stay allocated, f unchanged and the outputs unread, until tvspec_poll or
+ * tvspec_wait reports the ticket complete.  *ticket identifies it.
+ * Errors: TVSPEC_EINVAL (as tvspec_decompose_dev), TVSPEC_EBUSY (its
+ * working state exceeds the budget, or B*C would exceed the grid limit of a
+ * slot table), or the server's own failure code once it has failed.
+ */
+TVSPEC_API int tvspec_submit(tvspec_server *srv, const tvspec_request *req, unsigned long long *ticket);
+
+/*
+ * TVSPEC_PENDING while the request is queued or running; TVSPEC_OK once its
+ * outputs are complete on the device (the ticket is then retired and *res,
+ * if not NULL, holds its timings); a negative code if the server failed
+ * (tvspec_last_error() has the text) or the ticket is unknown (EINVAL).
+ */
+TVSPEC_API int tvspec_poll(tvspec_server *srv, unsigned long long ticket, tvspec_result *res);
+
+/* As tvspec_poll, but blocks until the request is complete or has failed. */
+TVSPEC_API int tvspec_wait(tvspec_server *srv, unsigned long long ticket, tvspec_result *res);
+
+/* Counters of the server so far. */
+TVSPEC_API int tvspec_server_info(tvspec_server *srv, tvspec_server_stats *info);
+
+/*
+ * Stop the worker, wait for the device work it enqueued, free the pool and
+ * the server.  Requests not yet complete are abandoned (their outputs are
+ * unspecified).  srv may be NULL.
+ */
+TVSPEC_API int tvspec_server_destroy(tvspec_server *srv);
 
 /*
  * Dyadic band edges (the paper groups unit-step bands dyadically, Sec. 4.1):

@@ -24,6 +24,8 @@ TVSPEC_EINVAL = -1
 TVSPEC_ENUMERIC = -2
 TVSPEC_ENOMEM = -3
 TVSPEC_EDEVICE = -4
+TVSPEC_EBUSY = -5
+TVSPEC_PENDING = 1
 TVSPEC_PRECISION_F32 = 0
 TVSPEC_PRECISION_F64 = 1
 TVSPEC_PRECISION_MIXED = 2
@@ -42,7 +44,33 @@ EXPORTS = (
     "tvspec_last_error",
     "tvspec_version",
     "tvspec_release",
+    "tvspec_server_create",
+    "tvspec_submit",
+    "tvspec_poll",
+    "tvspec_wait",
+    "tvspec_server_info",
+    "tvspec_server_destroy",
 )
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int), ("C", ctypes.c_int),
+                ("dt", ctypes.c_double), ("K", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("band_edges", ctypes.c_void_p), ("n_bands", ctypes.c_int),
+                ("bands", ctypes.c_void_p), ("S", ctypes.c_void_p), ("residual", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_ulonglong), ("admitted", ctypes.c_ulonglong),
+                ("completed", ctypes.c_ulonglong), ("steps", ctypes.c_ulonglong),
+                ("graph_builds", ctypes.c_ulonglong), ("buckets", ctypes.c_int),
+                ("max_in_flight", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
+                ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
 
 class TvspecError(RuntimeError):
@@ -75,6 +103,19 @@ def _load():
     lib.tvspec_version.restype = ctypes.c_char_p
     lib.tvspec_release.argtypes = []
     lib.tvspec_release.restype = None
+    ull = ctypes.c_ulonglong
+    lib.tvspec_server_create.argtypes = [ctypes.c_size_t, d, i, i, i, i, ctypes.POINTER(vp)]
+    lib.tvspec_server_create.restype = i
+    lib.tvspec_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ull)]
+    lib.tvspec_submit.restype = i
+    lib.tvspec_poll.argtypes = [vp, ull, ctypes.POINTER(_Result)]
+    lib.tvspec_poll.restype = i
+    lib.tvspec_wait.argtypes = [vp, ull, ctypes.POINTER(_Result)]
+    lib.tvspec_wait.restype = i
+    lib.tvspec_server_info.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+    lib.tvspec_server_info.restype = i
+    lib.tvspec_server_destroy.argtypes = [vp]
+    lib.tvspec_server_destroy.restype = i
     return lib
 
 
@@ -239,3 +280,142 @@ def tvspec_decompose_batch_dev(f: torch.Tensor, dt, K, inner_iters: int, band_ed
         bo += nbb * C * H * W
         so += C * Kb
     return out
+
+
+def tvspec_server_create(budget_bytes: int, tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = False,
+                         precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
+                         use_graphs: bool = True) -> ctypes.c_void_p:
+    """Create a server on the current device; returns its handle."""
+    h = ctypes.c_void_p()
+    _check(_lib.tvspec_server_create(int(budget_bytes), float(tau), 1 if warm_start else 0,
+                                     PRECISIONS[precision], int(iters_per_launch), 1 if use_graphs else 0,
+                                     ctypes.byref(h)))
+    return h
+
+
+def tvspec_submit(handle, f_ptr: int, H: int, W: int, C: int, dt: float, K: int, inner_iters: int,
+                  band_edges, bands_ptr: int, S_ptr: int, residual_ptr: int, stats_ptr: int) -> int:
+    """Queue a request given device pointers; returns its ticket."""
+    e = _edges_array(band_edges)
+    req = _Request(f_ptr, int(H), int(W), int(C), float(dt), int(K), int(inner_iters), e.ctypes.data,
+                   e.size - 1, bands_ptr, S_ptr, residual_ptr, stats_ptr)
+    t = ctypes.c_ulonglong(0)
+    _check(_lib.tvspec_submit(handle, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def _result(rc, r):
+    if rc == TVSPEC_PENDING:
+        return None
+    _check(rc)
+    return {"queue_ms": r.queue_ms, "latency_ms": r.latency_ms}
+
+
+def tvspec_poll(handle, ticket: int):
+    """None while pending, else {queue_ms, latency_ms} (the ticket is retired)."""
+    r = _Result()
+    return _result(_lib.tvspec_poll(handle, ctypes.c_ulonglong(ticket), ctypes.byref(r)), r)
+
+
+def tvspec_wait(handle, ticket: int):
+    """Block until complete; {queue_ms, latency_ms} (the ticket is retired)."""
+    r = _Result()
+    return _result(_lib.tvspec_wait(handle, ctypes.c_ulonglong(ticket), ctypes.byref(r)), r)
+
+
+def tvspec_server_info(handle) -> dict:
+    st = _ServerStats()
+    _check(_lib.tvspec_server_info(handle, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+
+def tvspec_server_destroy(handle) -> None:
+    _check(_lib.tvspec_server_destroy(handle))
+
+
+class Server:
+    """Continuous-batching decomposition server on the current device
+    (tvspec_server_create and friends).
+
+    submit() queues a (C,H,W) or (H,W) float32 GPU tensor and returns a ticket
+    and the output tensors it will fill; poll() / wait() report completion.
+    The binding keeps the request's tensors alive until its ticket completes.
+    Results equal tvspec_decompose_dev's with the server's options."""
+
+    def __init__(self, budget_bytes: int, tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = False,
+                 precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0, use_graphs: bool = True):
+        self._h = tvspec_server_create(budget_bytes, tau, warm_start, precision, iters_per_launch, use_graphs)
+        self._live = {}
+
+    def submit(self, f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges, sync: bool = True):
+        """Queue one image.  With sync=True (default) torch's current stream is
+        synchronised first, so that work writing f (and the allocation of the
+        outputs) is complete before the server's streams use them.  Returns
+        (ticket, outputs) with outputs a dict of bands (B,C,H,W), S (C,K),
+        residual (C,H,W) and stats (4,) device tensors."""
+        if self._h is None:
+            raise RuntimeError("server is closed")
+        if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32:
+            raise TypeError("f must be a float32 GPU tensor")
+        if f.dim() == 2:
+            f = f.unsqueeze(0)
+        if f.dim() != 3:
+            raise ValueError("f must be (C,H,W) or (H,W)")
+        f = f.contiguous()
+        C, H, W = f.shape
+        e = _edges_array(band_edges)
+        B = e.size - 1
+        dev = f.device
+        out = {
+            "bands": torch.empty((B, C, H, W), dtype=torch.float64, device=dev),
+            "S": torch.empty((C, int(K)), dtype=torch.float64, device=dev),
+            "residual": torch.empty((C, H, W), dtype=torch.float64, device=dev),
+            "stats": torch.empty((TVSPEC_NSTATS,), dtype=torch.float64, device=dev),
+        }
+        if sync:
+            torch.cuda.current_stream(dev).synchronize()
+        t = tvspec_submit(self._h, f.data_ptr(), H, W, C, dt, K, inner_iters, e, out["bands"].data_ptr(),
+                          out["S"].data_ptr(), out["residual"].data_ptr(), out["stats"].data_ptr())
+        self._live[t] = (f, out)
+        return t, out
+
+    def poll(self, ticket: int):
+        """None while pending; {queue_ms, latency_ms} once complete."""
+        try:
+            r = tvspec_poll(self._h, ticket)
+        except TvspecError:
+            self._live.pop(ticket, None)
+            raise
+        if r is not None:
+            self._live.pop(ticket, None)
+        return r
+
+    def wait(self, ticket: int):
+        """Block until the ticket completes; {queue_ms, latency_ms}."""
+        try:
+            return tvspec_wait(self._h, ticket)
+        finally:
+            self._live.pop(ticket, None)
+
+    def info(self) -> dict:
+        return tvspec_server_info(self._h)
+
+    def close(self) -> None:
+        if self._h is not None:
+            h, self._h = self._h, None
+            try:
+                tvspec_server_destroy(h)
+            finally:
+                self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

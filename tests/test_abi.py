@@ -119,6 +119,47 @@ def test_device_entry_validation_options():
     assert rc == -1
 
 
+def test_server_entry_validation():
+    """Server entry points reject bad options and null handles before any
+    device work."""
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.tvspec_server_create.argtypes = [ctypes.c_size_t, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    h = vp()
+    good = dict(budget=1 << 24, tau=0.248, warm=0, prec=2, ipl=0, graphs=1)
+    for bad in (dict(budget=1000), dict(tau=0.3), dict(warm=3), dict(prec=5), dict(ipl=9), dict(graphs=2)):
+        a = dict(good)
+        a.update(bad)
+        rc = lib.tvspec_server_create(a["budget"], a["tau"], a["warm"], a["prec"], a["ipl"], a["graphs"],
+                                      ctypes.byref(h))
+        assert rc == -1, bad
+        assert h.value is None
+    rc = lib.tvspec_server_create(1 << 24, 0.248, 0, 2, 0, 1, None)
+    assert rc == -1
+    lib.tvspec_submit.argtypes = [vp, vp, vp]
+    assert lib.tvspec_submit(None, None, None) == -1
+    lib.tvspec_poll.argtypes = [vp, ctypes.c_ulonglong, vp]
+    assert lib.tvspec_poll(None, 1, None) == -1
+    lib.tvspec_wait.argtypes = [vp, ctypes.c_ulonglong, vp]
+    assert lib.tvspec_wait(None, 1, None) == -1
+    lib.tvspec_server_info.argtypes = [vp, vp]
+    assert lib.tvspec_server_info(None, None) == -1
+    lib.tvspec_server_destroy.argtypes = [vp]
+    assert lib.tvspec_server_destroy(None) == 0
+
+
+def test_server_structs_match_header(tv):
+    """The binding's ctypes structures have the header's field order."""
+    text = open(HEADER).read()
+    for name, cls in (("tvspec_request", tv._Request), ("tvspec_result", tv._Result),
+                      ("tvspec_server_stats", tv._ServerStats)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"[\s\*]([A-Za-z_][A-Za-z_0-9]*)\s*(?=[,;])", body)
+        assert fields == [f for f, _ in cls._fields_], (name, fields)
+
+
 def test_product_path_never_reaches_the_oracle():
     """No module of the package, nor the HIP source, imports or links the
     oracle; there is no CPU fallback."""
