@@ -111,6 +111,124 @@ def batch_throughput(n, precision):
             "workload": "64x64 shape images, dt 0.005, K 60, 200 iterations, 4 dyadic bands"}
 
 
+SERVING = {
+    "workload": "continuous-batching server, 3-channel synthetic shape images (40 shapes, size scaled "
+                "with the side), side uniform in {128, 256, 512, 1024}, Poisson arrivals",
+    "C": 3, "sides": [128, 256, 512, 1024], "dt": 0.005, "K": 100, "inner_iters": 150, "n_bands": 4,
+}
+
+
+def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
+    """The serving workload through the server: first a burst of `burst`
+    requests submitted at once (sustainable throughput), then n_req requests
+    with Poisson arrivals at `rate` per second (0: 85% of the burst's
+    request rate).  Inputs (a pool of `pool` images per side) and every
+    request's outputs are resident in HBM before the timed region.  Latency
+    is the server's own submission-to-completion time per request."""
+    import threading
+
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import synth, tvspec
+
+    sv = SERVING
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    imgs = {s: [torch.from_numpy(synth.shapes_image(synth.serving_spec(s), 10000 * s + i)).to(dev)
+                for i in range(pool)] for s in sv["sides"]}
+    edges = tvspec.tvspec_dyadic_edges(sv["K"], sv["n_bands"])
+    C, K = sv["C"], sv["K"]
+
+    def make_jobs(n):
+        sides = rng.choice(sv["sides"], size=n)
+        jobs = []
+        for i, s in enumerate(sides):
+            s = int(s)
+            out = {"bands": torch.empty((sv["n_bands"], C, s, s), dtype=torch.float64, device=dev),
+                   "S": torch.empty((C, K), dtype=torch.float64, device=dev),
+                   "residual": torch.empty((C, s, s), dtype=torch.float64, device=dev),
+                   "stats": torch.empty((tvspec.TVSPEC_NSTATS,), dtype=torch.float64, device=dev)}
+            jobs.append((s, imgs[s][i % pool], out))
+        return jobs
+
+    def run(srv, jobs, arrivals):
+        """Submit job i at arrivals[i] seconds; collect completions."""
+        done = {}
+        tickets = [None] * len(jobs)
+        t_sub = [0.0] * len(jobs)
+        finished = threading.Event()
+
+        def collect():
+            while len(done) < len(jobs):
+                progressed = False
+                for i, t in enumerate(tickets):
+                    if t is not None and i not in done:
+                        r = srv.poll(t)
+                        if r is not None:
+                            done[i] = r
+                            progressed = True
+                if not progressed:
+                    time.sleep(0.0005)
+            finished.set()
+
+        th = threading.Thread(target=collect, daemon=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th.start()
+        for i, (s, f, out) in enumerate(jobs):
+            while True:
+                d = t0 + arrivals[i] - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.001))
+            t_sub[i] = time.perf_counter() - t0
+            tickets[i] = srv.submit(f, sv["dt"], K, sv["inner_iters"], edges, sync=False, out=out)[0]
+        finished.wait(timeout=600)
+        th.join(timeout=1)
+        if len(done) < len(jobs):
+            raise RuntimeError("serving bench: requests did not complete")
+        lat = [done[i]["latency_ms"] for i in range(len(jobs))]
+        end = max(t_sub[i] + lat[i] / 1e3 for i in range(len(jobs)))
+        px = sum(s * s for s, _, _ in jobs)
+        per_side = {}
+        for side in sv["sides"]:
+            ls = [lat[i] for i, (s, _, _) in enumerate(jobs) if s == side]
+            if ls:
+                per_side[str(side)] = {"n": len(ls), "p50_ms": percentile(ls, 50), "p99_ms": percentile(ls, 99)}
+        worst = max(float(out["stats"][0]) for _, _, out in jobs)
+        return {"requests": len(jobs), "makespan_s": end, "MPix_per_s": px / 1e6 / end,
+                "channel_MPix_per_s": C * px / 1e6 / end, "req_per_s": len(jobs) / end,
+                "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                "mean_ms": float(np.mean(lat)), "queue_p99_ms": percentile([done[i]["queue_ms"] for i in done], 99),
+                "per_side": per_side, "max_recon_err": worst}
+
+    budget = int(budget_gb * (1 << 30))
+    rec = {"workload": sv["workload"], "config": {k: v for k, v in sv.items() if k != "workload"},
+           "precision": precision, "budget_GiB": budget_gb}
+    with tvspec.Server(budget, precision=precision) as srv:
+        # warm the buckets (graphs, autotuner) on a few requests of every side
+        warm = [(s, imgs[s][0], None) for s in sv["sides"]]
+        for s, f, _ in warm:
+            srv.submit(f, sv["dt"], 2, sv["inner_iters"], [0, 2])
+        while srv.info()["completed"] < len(warm):
+            time.sleep(0.001)
+        jobs = make_jobs(burst)
+        sat = run(srv, jobs, [0.0] * burst)
+        del jobs
+        rec["saturated"] = sat
+        print("bench: serving burst done (%.2f req/s)" % sat["req_per_s"], file=sys.stderr, flush=True)
+        r = rate if rate > 0 else 0.85 * sat["req_per_s"]
+        jobs = make_jobs(n_req)
+        arrivals = np.cumsum(rng.exponential(1.0 / r, size=n_req))
+        arrivals -= arrivals[0]
+        rec["poisson"] = run(srv, jobs, list(arrivals))
+        rec["poisson"]["rate_req_per_s"] = r
+        del jobs
+        info = srv.info()
+    rec["server"] = {k: info[k] for k in ("max_in_flight", "graph_builds", "buckets", "steps", "peak_bytes")}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +239,13 @@ def main():
     ap.add_argument("--latency-calls", type=int, default=20)
     ap.add_argument("--batch-images", type=int, default=256,
                     help="also time one batched call over this many 64x64 images (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the Poisson serving run (0 = skip the serving benchmark)")
+    ap.add_argument("--serve-burst", type=int, default=64,
+                    help="requests of the saturating burst that precedes it")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate, requests/s (0 = 85%% of the burst's rate)")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -246,6 +371,11 @@ def main():
     if args.batch_images > 0:
         rec["batch_64x64"] = batch_throughput(args.batch_images, args.precision)
         print("bench: batched 64x64 pass done", file=sys.stderr, flush=True)
+
+    if args.serve_requests > 0:
+        rec["serving"] = serving_bench(args.serve_requests, args.serve_rate, args.serve_burst,
+                                       args.serve_budget_gb, args.precision)
+        print("bench: serving pass done", file=sys.stderr, flush=True)
 
     # the host entry point (host buffers, PCIe-inclusive), once, for reference
     t1 = time.perf_counter()

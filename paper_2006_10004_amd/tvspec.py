@@ -168,6 +168,18 @@ def _edges_array(edges):
     return e
 
 
+def _outputs(out, B, C, H, W, K, dev):
+    """New output tensors, or a check of caller-provided ones."""
+    want = {"bands": (B, C, H, W), "S": (C, K), "residual": (C, H, W), "stats": (TVSPEC_NSTATS,)}
+    if out is None:
+        return {k: torch.empty(shp, dtype=torch.float64, device=dev) for k, shp in want.items()}
+    for k, shp in want.items():
+        t = out[k]
+        if tuple(t.shape) != shp or t.dtype != torch.float64 or t.device != dev or not t.is_contiguous():
+            raise ValueError("out[%r] must be a contiguous float64 %s tensor on %s" % (k, shp, dev))
+    return out
+
+
 def tvspec_decompose(f: np.ndarray, dt: float, K: int, inner_iters: int, band_edges):
     """Host entry point (synchronous, default options).
 
@@ -212,19 +224,7 @@ def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, b
     B = e.size - 1
     prec = PRECISIONS[precision]
     dev = f.device
-    if out is None:
-        out = {
-            "bands": torch.empty((B, C, H, W), dtype=torch.float64, device=dev),
-            "S": torch.empty((C, K), dtype=torch.float64, device=dev),
-            "residual": torch.empty((C, H, W), dtype=torch.float64, device=dev),
-            "stats": torch.empty((TVSPEC_NSTATS,), dtype=torch.float64, device=dev),
-        }
-    else:
-        want = {"bands": (B, C, H, W), "S": (C, K), "residual": (C, H, W), "stats": (TVSPEC_NSTATS,)}
-        for k, shp in want.items():
-            t = out[k]
-            if tuple(t.shape) != shp or t.dtype != torch.float64 or t.device != dev or not t.is_contiguous():
-                raise ValueError("out[%r] must be a contiguous float64 %s tensor on %s" % (k, shp, dev))
+    out = _outputs(out, B, C, H, W, int(K), dev)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     with torch.cuda.device(dev):
         _check(_lib.tvspec_decompose_dev(
@@ -347,12 +347,14 @@ class Server:
         self._h = tvspec_server_create(budget_bytes, tau, warm_start, precision, iters_per_launch, use_graphs)
         self._live = {}
 
-    def submit(self, f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges, sync: bool = True):
+    def submit(self, f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges, sync: bool = True,
+               out: dict | None = None):
         """Queue one image.  With sync=True (default) torch's current stream is
         synchronised first, so that work writing f (and the allocation of the
         outputs) is complete before the server's streams use them.  Returns
         (ticket, outputs) with outputs a dict of bands (B,C,H,W), S (C,K),
-        residual (C,H,W) and stats (4,) device tensors."""
+        residual (C,H,W) and stats (4,) device tensors (`out` may pass
+        preallocated ones of those shapes)."""
         if self._h is None:
             raise RuntimeError("server is closed")
         if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32:
@@ -366,12 +368,7 @@ class Server:
         e = _edges_array(band_edges)
         B = e.size - 1
         dev = f.device
-        out = {
-            "bands": torch.empty((B, C, H, W), dtype=torch.float64, device=dev),
-            "S": torch.empty((C, int(K)), dtype=torch.float64, device=dev),
-            "residual": torch.empty((C, H, W), dtype=torch.float64, device=dev),
-            "stats": torch.empty((TVSPEC_NSTATS,), dtype=torch.float64, device=dev),
-        }
+        out = _outputs(out, B, C, H, W, int(K), dev)
         if sync:
             torch.cuda.current_stream(dev).synchronize()
         t = tvspec_submit(self._h, f.data_ptr(), H, W, C, dt, K, inner_iters, e, out["bands"].data_ptr(),
