@@ -126,10 +126,13 @@ TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
  *                     change of one input pixel, against ~3e-7 cold.
  *   precision         TVSPEC_PRECISION_F32, _F64 or _MIXED
  *   iters_per_launch  temporal blocking factor: Chambolle iterations done per
- *                     kernel launch on an LDS-resident tile (0 = automatic,
- *                     else 1..16 for F32, 1..8 for F64 and MIXED).  Results do not
- *                     depend on it: every variant applies the same per-pixel
- *                     arithmetic in the same order.
+ *                     kernel launch on an LDS-resident tile (1..16 for F32,
+ *                     1..8 for F64 and MIXED; 0 = automatic: 8 for F32, 5 for
+ *                     F64, and for MIXED 5 when a launch has at least two
+ *                     workgroups per compute unit (several images or
+ *                     channels, or planes above ~512x512), else 8).  Results
+ *                     do not depend on it: every variant applies the same
+ *                     per-pixel arithmetic in the same order.
  *   stats             TVSPEC_NSTATS doubles (device): [0] max |f - sum of
  *                     bands - residual|, [1] max over channels of
  *                     |mean(u_{K+1}) - mean(f_c)|, [2] number of non-finite

@@ -74,9 +74,9 @@ struct StepConfig {
     int timed = 1;        // 0: never record benchmark timing (graph capture)
 };
 
-// Tile-kernel launches per engine_step (the dual-field parity flips after a
-// step when this is odd).
-int tile_launches_per_step(const StepConfig &cfg);
+// Tile-kernel launches per engine_step over a table of nslots slots (the
+// dual-field parity flips after a step when this is odd).
+int tile_launches_per_step(const StepConfig &cfg, int nslots);
 
 // u_0 = f, G = grad(f)/dt, p = 0, bands = 0, k_cur = 0, active = 1, for
 // slots [first, first + count) of the table.

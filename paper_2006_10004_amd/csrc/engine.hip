@@ -221,36 +221,41 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
 // the small gradients of flat regions, whereas G carries only the relative
 // rounding of the gradient itself.
 //
-// Grid: (number of BX x BY output tiles, slots * C); 1024 threads, so that every
-// SIMD of the CU has four waves to interleave (the per-pixel chain of LDS
-// reads, square root and reciprocal is long and a tile holds few pixels).
-// The workgroup stages the (BX+2TB) x (BY+2TB) region around its tile: the
-// dual field and G of every region pixel live in registers of the thread
-// that owns the pixel for all `iters` iterations; LDS only carries the
-// values a neighbour needs (px of the left pixel and py of the upper one for
-// div p, div p of the right and lower pixels for its gradient).  The LDS
-// planes carry a one-pixel ring that is never written, so neighbour reads
-// need no tests.  One iteration on every region pixel:
+// Grid: (number of BX x BY output tiles, slots * C); NT threads (1024 by
+// default, so that every SIMD of the CU has four waves to interleave: the
+// per-pixel chain of LDS reads, square root and reciprocal is long and a tile
+// holds few pixels).  The workgroup stages the (BX+2TB) x (BY+2TB) region
+// around its tile: the dual field and G of every region pixel live in
+// registers of the thread that owns the pixel for all `iters` iterations;
+// LDS only carries the values a neighbour needs.  The LDS planes carry a
+// one-pixel ring that is never written, so neighbour reads need no tests.
+// One iteration on every region pixel:
 //     d   = (px - px_left) + (py - py_up)                      (div p)
 //     a   = ((d_right - d) - Gx, (d_down - d) - Gy), zero on the last
 //           column / row and outside the image
 //     p  <- (p + tau a) / (1 + tau |a|)
+// Two forms of the iteration, with identical arithmetic per pixel:
+//   OB = false  two barriers per iteration: d goes through LDS (px of the
+//               left pixel and py of the upper one for d, then d of the right
+//               and lower pixels for a);
+//   OB = true   one barrier per iteration: the dual field is double-buffered
+//               in LDS and each pixel forms d_right and d_down itself from the
+//               previous iterate, with the operations (and their order) the
+//               right and lower pixels use for their own d.
 // Pixels outside the image start with p = 0 and a = 0, so they keep p = 0;
 // that realises the Neumann divergence (p_x = 0 on the last column and
 // p_y = 0 on the last row is preserved by the update because a_x, a_y vanish
 // there).  With zero_in set (first launch of a cold-started solve) the
 // incoming dual field is taken as zero instead of being read.  The dual field
 // is read from buffer `cur` of the slot and written to buffer 1 - cur.
-// Channel planes of slots whose flow is complete (inactive) are skipped.  A region
-// pixel at distance e from the region edge is exact while the iteration
-// count is <= e, so after iters <= TB iterations the BX x BY centre is exact
-// and is written.
-constexpr int kTileThreads = 1024;
-
-template <typename S, typename M, int BX, int BY, int TB>
-__global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc *__restrict__ slots, int cur, int H,
-                                                                int W, int C, int ntx, int ntiles, S tau, int iters,
-                                                                int zero_in)
+// Channel planes of slots whose flow is complete (inactive) are skipped.
+// The new dual vector of a pixel depends on the previous iterate within one
+// pixel (either form), so a region pixel at distance e from the region edge
+// is exact while the iteration count is <= e: after iters <= TB iterations
+// the BX x BY centre is exact and is written.
+template <typename S, typename M, int BX, int BY, int TB, int NT, bool OB>
+__global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restrict__ slots, int cur, int H, int W,
+                                                      int C, int ntx, int ntiles, S tau, int iters, int zero_in)
 {
     const int slot = blockIdx.y / C;
     const int chan = blockIdx.y - slot * C;
@@ -262,10 +267,11 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
     constexpr int RN = RX * RY;
     constexpr int LX = RX + 2;            // LDS row pitch: region + zero ring
     constexpr int LN = LX * (RY + 2);
-    constexpr int PPT = (RN + kTileThreads - 1) / kTileThreads;
-    __shared__ S s_px[LN];
-    __shared__ S s_py[LN];
-    __shared__ S s_d[LN];
+    constexpr int PPT = (RN + NT - 1) / NT;
+    constexpr int NB = OB ? 2 : 1;        // dual-field LDS buffers
+    __shared__ S s_px[NB][LN];
+    __shared__ S s_py[NB][LN];
+    __shared__ S s_d[OB ? 1 : LN];
 
     const size_t plane = (size_t)H * (size_t)W;
     const size_t coff = (size_t)chan * plane;
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
     const int ox = tx * BX - TB;
 
     // zero ring (read by the outermost region pixels only)
-    for (int e = threadIdx.x; e < 2 * LX + 2 * RY; e += kTileThreads) {
+    for (int e = threadIdx.x; e < 2 * LX + 2 * RY; e += NT) {
         int li;
         if (e < LX)
             li = e;                              // top row
@@ -296,9 +302,13 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
             li = (e - 2 * LX + 1) * LX;          // left column
         else
             li = (e - 2 * LX - RY + 1) * LX + LX - 1; // right column
-        s_px[li] = S(0);
-        s_py[li] = S(0);
-        s_d[li] = S(0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            s_px[k][li] = S(0);
+            s_py[k][li] = S(0);
+        }
+        if constexpr (!OB)
+            s_d[li] = S(0);
     }
 
     S px[PPT], py[PPT], d[PPT], gx[PPT], gy[PPT];
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
     S my[PPT];       // 1 where a_y is live (inside the image, not its last row), else 0
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        const int idx = threadIdx.x + m * kTileThreads;
+        const int idx = threadIdx.x + m * NT;
         S vx = S(0), vy = S(0);
         M vgx = M(0), vgy = M(0);
         bool ax_live = false, ay_live = false;
@@ -329,8 +339,8 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
                 ax_live = gj < W - 1;
                 ay_live = gi < H - 1;
             }
-            s_px[l] = vx;
-            s_py[l] = vy;
+            s_px[0][l] = vx;
+            s_py[0][l] = vy;
         }
         li[m] = l;
         px[m] = vx;
@@ -343,39 +353,69 @@ __global__ __launch_bounds__(kTileThreads) void k_chambolle_tile(const SlotDesc 
     }
     __syncthreads();
 
-    for (int it = 0; it < iters; ++it) {
+    if constexpr (OB) {
+        for (int it = 0; it < iters; ++it) {
+            const S *__restrict__ qx = s_px[it & 1];
+            const S *__restrict__ qy = s_py[it & 1];
+            S *__restrict__ wx = s_px[(it & 1) ^ 1];
+            S *__restrict__ wy = s_py[(it & 1) ^ 1];
 #pragma unroll
-        for (int m = 0; m < PPT; ++m) {
-            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
-                const int l = li[m];
-                const S dv = (px[m] - s_px[l - 1]) + (py[m] - s_py[l - LX]);
-                d[m] = dv;
-                s_d[l] = dv;
+            for (int m = 0; m < PPT; ++m) {
+                if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+                    const int l = li[m];
+                    // the previous iterate around the pixel: unconditional
+                    // LDS reads, boundary masks multiply
+                    const S pxl = qx[l - 1], pxr = qx[l + 1];
+                    const S pxd = qx[l + LX], pxdl = qx[l + LX - 1];
+                    const S pyu = qy[l - LX], pyur = qy[l - LX + 1];
+                    const S pyr = qy[l + 1], pyd = qy[l + LX];
+                    const S dv = (px[m] - pxl) + (py[m] - pyu);
+                    const S dr = (pxr - px[m]) + (pyr - pyur);
+                    const S dd = (pxd - pxdl) + (pyd - py[m]);
+                    const S ax = ((dr - dv) - gx[m]) * mx[m];
+                    const S ay = ((dd - dv) - gy[m]) * my[m];
+                    chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
+                    wx[l] = px[m];
+                    wy[l] = py[m];
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int m = 0; m < PPT; ++m) {
-            if (m < PPT - 1 || threadIdx.x + m * kTileThreads < RN) {
-                const int l = li[m];
-                // unconditional LDS reads; the boundary masks multiply (a
-                // select around the reads compiles to branches that expose
-                // the LDS latency of every pixel)
-                const S dr = s_d[l + 1];
-                const S dd = s_d[l + LX];
-                const S ax = ((dr - d[m]) - gx[m]) * mx[m];
-                const S ay = ((dd - d[m]) - gy[m]) * my[m];
-                chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
-                s_px[l] = px[m];
-                s_py[l] = py[m];
+            for (int m = 0; m < PPT; ++m) {
+                if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+                    const int l = li[m];
+                    const S dv = (px[m] - s_px[0][l - 1]) + (py[m] - s_py[0][l - LX]);
+                    d[m] = dv;
+                    s_d[l] = dv;
+                }
             }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+                    const int l = li[m];
+                    // unconditional LDS reads; the boundary masks multiply (a
+                    // select around the reads compiles to branches that expose
+                    // the LDS latency of every pixel)
+                    const S dr = s_d[l + 1];
+                    const S dd = s_d[l + LX];
+                    const S ax = ((dr - d[m]) - gx[m]) * mx[m];
+                    const S ay = ((dd - d[m]) - gy[m]) * my[m];
+                    chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
+                    s_px[0][l] = px[m];
+                    s_py[0][l] = py[m];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        const int idx = threadIdx.x + m * kTileThreads;
+        const int idx = threadIdx.x + m * NT;
         if (idx < RN) {
             const int ri = idx / RX;
             const int rj = idx - ri * RX;
@@ -579,8 +619,11 @@ __global__ __launch_bounds__(kThreads) void k_report(const SlotDesc *__restrict_
 // ---------------------------------------------------------------------------
 // launch configuration
 
+// Output tile of the Chambolle kernel, its workgroup size and iteration form.
 constexpr int kTileX = 32;
 constexpr int kTileY = 32;
+constexpr int kTileThreads = 1024;
+constexpr bool kOneBarrier = false;
 
 int blocks_for(size_t n, int cap)
 {
@@ -600,14 +643,49 @@ template <typename S> constexpr int max_tb() { return std::is_same<S, float>::va
 // Smallest compiled halo width >= t.
 template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
-    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1>; }
-    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2>; }
-    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4>; }
+    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1, kTileThreads, kOneBarrier>; }
+    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2, kTileThreads, kOneBarrier>; }
+    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4, kTileThreads, kOneBarrier>; }
+    if (t <= 5) { *tb = 5; return k_chambolle_tile<S, M, kTileX, kTileY, 5, kTileThreads, kOneBarrier>; }
     if constexpr (max_tb<S>() >= 16) {
-        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16>; }
+        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16, kTileThreads, kOneBarrier>; }
     }
     *tb = 8;
-    return k_chambolle_tile<S, M, kTileX, kTileY, 8>;
+    return k_chambolle_tile<S, M, kTileX, kTileY, 8, kTileThreads, kOneBarrier>;
+}
+
+// Compute units of the current device (cached per device).
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+// Automatic temporal blocking factor.  The 32x32 tile with TB = 8 stages a
+// 48x48 region (2.25 region pixels per output pixel, 70 VGPRs in MIXED): one
+// 1024-thread workgroup per CU.  TB = 5 stages 42x42 (1.72 per output
+// pixel, 52 VGPRs, 46 KB LDS), which lets two workgroups share a CU and hide
+// each other's barriers and loads, at 8/5 the launches.  Measured on MI355X
+// (MIXED): a launch that gives every CU at least two workgroups runs ~30%
+// faster with TB = 5; with one workgroup per CU (a single 512x512 plane)
+// TB = 8 is ~3% faster.  F64 favours TB = 5 in both regimes; F32 keeps
+// TB = 8.
+int auto_tb(int precision, long long workgroups)
+{
+    if (precision == TVSPEC_PRECISION_F32)
+        return 8;
+    if (precision == TVSPEC_PRECISION_F64)
+        return 5;
+    return workgroups >= 2LL * device_cus() ? 5 : 8;
 }
 
 // ---------------------------------------------------------------------------
@@ -668,13 +746,14 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
                                                 hipStream_t st, long long live_planes)
 {
     const int plane = cfg.H * cfg.W;
-    int tb = 0;
-    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : 8;
-    TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
-    const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
     const int ntx = (cfg.W + kTileX - 1) / kTileX;
     const int nty = (cfg.H + kTileY - 1) / kTileY;
     const int ntiles = ntx * nty;
+    int tb = 0;
+    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
+                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C);
+    TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
+    const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
     int cur = *parity;
 
     // timing: one event pair around the back-to-back Chambolle launches of
@@ -758,10 +837,12 @@ void band_rows_of(const int *edges, int nbands, int *rows)
             rows[k] = j;
 }
 
-int tile_launches_per_step(const StepConfig &cfg)
+int tile_launches_per_step(const StepConfig &cfg, int nslots)
 {
+    const int ntiles = ((cfg.W + kTileX - 1) / kTileX) * ((cfg.H + kTileY - 1) / kTileY);
     int tb = 0;
-    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : 8;
+    const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
+                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C);
     if (cfg.precision == TVSPEC_PRECISION_F32)
         (void)tile_kernel<float, float>(want, &tb);
     else

@@ -251,7 +251,7 @@ int bucket_for(tvspec_server *s, const Request &q, int *out)
     HIP_TRY(hipMemsetAsync(b->table, 0, (size_t)b->cap * sizeof(SlotDesc), b->st));
     if (s->ipl == 0) {
         b->tuning = true;
-        b->cand = s->precision == TVSPEC_PRECISION_F32 ? std::vector<int>{4, 8, 16} : std::vector<int>{4, 8};
+        b->cand = s->precision == TVSPEC_PRECISION_F32 ? std::vector<int>{4, 8, 16} : std::vector<int>{4, 5, 8};
         b->cfg.iters_per_launch = b->cand[0];
     }
     s->buckets.push_back(std::move(b));
@@ -415,7 +415,7 @@ int step_bucket(tvspec_server *s, Bucket &b)
         if (timing)
             HIP_TRY(hipEventRecord(ta, b.st));
         HIP_TRY(hipGraphLaunch(ex, b.st));
-        b.parity ^= (tile_launches_per_step(cfg) & 1);
+        b.parity ^= (tile_launches_per_step(cfg, n) & 1);
     } else {
         if (timing)
             HIP_TRY(hipEventRecord(ta, b.st));
