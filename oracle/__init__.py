@@ -11,10 +11,13 @@ citations of the paper are in the C source:
   grad / div      discrete isotropic TV in dual form, Sec. 2.1 Eq. (2)
   rof             implicit Euler step of Eq. (1) = ROF problem Eq. (8),
                   Chambolle's dual fixed point (the solver named in Sec. 4.3)
+  rof_pdhg        the same ROF problem by the Chambolle-Pock primal-dual
+                  algorithm (the paper's GPU baseline solver, Sec. 4.3)
   tv_flow         the flow u_0 = f, u_{s+1} = ROF(u_s, dt)
   spectral        phi = t u_tt Eq. (3), S(t) = ||phi||_1, bands Eq. (7),
                   residual Eq. (5)
-  decompose       tv_flow followed by spectral, per channel
+  decompose       tv_flow followed by spectral, per channel, with either
+                  ROF solver
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, invariants and brute force, except the finite-iteration
@@ -35,6 +38,9 @@ _fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 
 DEFAULT_TAU = 0.248
+# primal-dual steps tau = sigma = 1/sqrt(8): tau sigma ||grad||^2 <= 1
+PDHG_STEP = 1.0 / np.sqrt(8.0)
+SOLVERS = {"chambolle": 0, "pdhg": 1}
 
 
 def _load():
@@ -64,6 +70,10 @@ def _load():
     lib.orc_edges_valid.restype = i
     lib.orc_decompose.argtypes = [_fp, i, i, i, d, i, i, d, i, _ip, i, _dp, _dp, _dp, _dp]
     lib.orc_decompose.restype = i
+    lib.orc_rof_pdhg.argtypes = [_dp, i, i, d, d, d, i, _dp, _dp, _dp]
+    lib.orc_rof_pdhg.restype = None
+    lib.orc_decompose_solver.argtypes = [_fp, i, i, i, d, i, i, i, d, d, i, _ip, i, _dp, _dp, _dp, _dp]
+    lib.orc_decompose_solver.restype = i
     _lib = lib
     return lib
 
@@ -119,6 +129,19 @@ def rof(g, lam, iters, tau=DEFAULT_TAU, px=None, py=None):
     return v, px, py
 
 
+def rof_pdhg(g, lam, iters, tau=PDHG_STEP, sigma=PDHG_STEP, yx=None, yy=None):
+    """Chambolle-Pock primal-dual iteration for min 0.5||g-v||^2 + lam TV(v),
+    from x = xbar = g.  Returns (v, yx, yy); (yx, yy) start at zero unless
+    given."""
+    g = _plane(g)
+    H, W = g.shape
+    yx = np.zeros_like(g) if yx is None else np.array(yx, dtype=np.float64, order="C")
+    yy = np.zeros_like(g) if yy is None else np.array(yy, dtype=np.float64, order="C")
+    v = np.empty_like(g)
+    _load().orc_rof_pdhg(g, H, W, float(lam), float(tau), float(sigma), int(iters), yx, yy, v)
+    return v, yx, yy
+
+
 def tv_flow(f, dt, nsteps, iters, tau=DEFAULT_TAU, warm=False):
     """States u_0..u_nsteps of the implicit-Euler TV flow, shape (nsteps+1, H, W).
 
@@ -152,11 +175,13 @@ def spectral(states, dt, K, edges, want_phi=False):
     return {"S": S, "bands": bands, "residual": res, "phi": phi}
 
 
-def decompose(f, dt, K, iters, edges, tau=DEFAULT_TAU, warm=False):
+def decompose(f, dt, K, iters, edges, tau=None, warm=False, solver="chambolle", sigma=None):
     """Full decomposition of a (C,H,W) or (H,W) float32 image.
 
     warm=False (default): every ROF solve starts its dual field at zero (the
     paper does not say how the dual field is initialised; see tv_flow).
+    solver "chambolle" (step tau, default 0.248) or "pdhg" (steps tau and
+    sigma, default 1/sqrt(8) each).
 
     Returns dict(bands (B,C,H,W), S (C,K), residual (C,H,W), recon_err, mean_err)."""
     f = np.asarray(f)
@@ -170,8 +195,13 @@ def decompose(f, dt, K, iters, edges, tau=DEFAULT_TAU, warm=False):
     S = np.empty((C, K))
     res = np.empty((C, H, W))
     rep = np.empty(2)
-    rc = _load().orc_decompose(f, H, W, C, float(dt), int(K), int(iters), float(tau),
-                               1 if warm else 0, e, B, bands, S, res, rep)
+    sv = SOLVERS[solver]
+    if tau is None:
+        tau = PDHG_STEP if sv == 1 else DEFAULT_TAU
+    if sigma is None:
+        sigma = PDHG_STEP if sv == 1 else 0.0
+    rc = _load().orc_decompose_solver(f, H, W, C, float(dt), int(K), int(iters), sv, float(tau), float(sigma),
+                                      1 if warm else 0, e, B, bands, S, res, rep)
     if rc != 0:
         raise ValueError("invalid arguments to the oracle decomposition")
     return {"bands": bands, "S": S, "residual": res,

@@ -159,6 +159,62 @@ void orc_rof(const double *g, int H, int W, double lambda, double tau, int iters
     free(ay);
 }
 
+/* The same ROF problem by the first-order primal-dual algorithm of
+ * Chambolle and Pock (2011, Algorithm 1; the paper's GPU baseline is a
+ * primal-dual solver, Sec. 4.3), with operator grad, F = lambda ||.||_{2,1}
+ * on the gradient field and G(v) = 0.5 ||v - g||^2:
+ *     y    <- proj(y + sigma grad xbar),  proj(y) = y / max(1, |y| / lambda)
+ *     x'   <- (x + tau div y + tau g) / (1 + tau)
+ *     xbar <- x' + theta (x' - x),  theta = 1;   x <- x'
+ * starting from x = xbar = g and the given y; v receives x after `iters`
+ * iterations.  Convergence needs tau sigma ||grad||^2 <= 1 (||grad||^2 <=
+ * 8).  (yx, yy) hold the starting dual field on entry and the final one on
+ * exit. */
+void orc_rof_pdhg(const double *g, int H, int W, double lambda, double tau, double sigma,
+                  int iters, double *yx, double *yy, double *v)
+{
+    size_t n = (size_t)H * (size_t)W;
+    double *x = (double *)malloc(n * sizeof(double));
+    double *xb = (double *)malloc(n * sizeof(double));
+    double *ax = (double *)malloc(n * sizeof(double));
+    double *ay = (double *)malloc(n * sizeof(double));
+    double *d = (double *)malloc(n * sizeof(double));
+    memcpy(x, g, n * sizeof(double));
+    memcpy(xb, g, n * sizeof(double));
+    for (int it = 0; it < iters; ++it) {
+        orc_grad(xb, H, W, ax, ay);
+        int i;
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < H; ++i) {
+            for (int j = 0; j < W; ++j) {
+                size_t q = IDX(i, j);
+                double zx = yx[q] + sigma * ax[q];
+                double zy = yy[q] + sigma * ay[q];
+                double m = sqrt(zx * zx + zy * zy) / lambda;
+                double s = m > 1.0 ? m : 1.0;
+                yx[q] = zx / s;
+                yy[q] = zy / s;
+            }
+        }
+        orc_div(yx, yy, H, W, d);
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < H; ++i) {
+            for (int j = 0; j < W; ++j) {
+                size_t q = IDX(i, j);
+                double xn = (x[q] + tau * d[q] + tau * g[q]) / (1.0 + tau);
+                xb[q] = xn + 1.0 * (xn - x[q]);
+                x[q] = xn;
+            }
+        }
+    }
+    memcpy(v, x, n * sizeof(double));
+    free(x);
+    free(xb);
+    free(ax);
+    free(ay);
+    free(d);
+}
+
 /* TV flow Eq. (1) by implicit Euler: u_0 = f, u_{s+1} = ROF(u_s, dt) for
  * s = 0..nsteps-1.  states receives u_0..u_nsteps, (nsteps+1) planes of H*W.
  * warm == 0: every solve starts its dual field from zero; warm != 0: the
@@ -236,8 +292,21 @@ int orc_edges_valid(int K, const int *edges, int nbands)
     return 1;
 }
 
+/* One ROF solve of the flow by the selected solver: 0 = Chambolle's dual
+ * fixed point (step tau), 1 = Chambolle-Pock primal-dual (steps tau, sigma);
+ * (px, py) is the dual field carried between solves. */
+static void rof_solve(int solver, const double *g, int H, int W, double lambda, double tau,
+                      double sigma, int iters, double *px, double *py, double *v)
+{
+    if (solver == 1)
+        orc_rof_pdhg(g, H, W, lambda, tau, sigma, iters, px, py, v);
+    else
+        orc_rof(g, H, W, lambda, tau, iters, px, py, v);
+}
+
 /* Full decomposition of a C x H x W float image (channels independent).
- * Same quantities as orc_tv_flow followed by orc_spectral, but the flow is
+ * Same quantities as orc_tv_flow followed by orc_spectral (the ROF solves by
+ * `solver`, as rof_solve), but the flow is
  * walked one step at a time with only u_{k-1}, u_k, u_{k+1} kept, so large
  * images do not need all K+2 states in memory.
  *   bands    [nbands][C][H][W]
@@ -246,11 +315,12 @@ int orc_edges_valid(int K, const int *edges, int nbands)
  *   report   [2]: max |f - sum bands - residual|, and
  *                 max over c of |mean(u_{K+1}) - mean(f_c)|.
  * Returns 0, or -1 on invalid arguments. */
-int orc_decompose(const float *f, int H, int W, int C, double dt, int K, int iters,
-                  double tau, int warm, const int *edges, int nbands,
-                  double *bands, double *S, double *residual, double *report)
+int orc_decompose_solver(const float *f, int H, int W, int C, double dt, int K, int iters,
+                         int solver, double tau, double sigma, int warm, const int *edges,
+                         int nbands, double *bands, double *S, double *residual, double *report)
 {
     if (H < 2 || W < 2 || C < 1 || K < 1 || iters < 1 || !(dt > 0.0) || !(tau > 0.0) ||
+        (solver != 0 && solver != 1) || (solver == 1 && !(sigma > 0.0)) ||
         !orc_edges_valid(K, edges, nbands))
         return -1;
     size_t n = (size_t)H * (size_t)W;
@@ -270,7 +340,7 @@ int orc_decompose(const float *f, int H, int W, int C, double dt, int K, int ite
         for (size_t q = 0; q < n; ++q)
             u0[q] = (double)fc[q];
         /* u_0 -> u_1 */
-        orc_rof(u0, H, W, dt, tau, iters, px, py, up);
+        rof_solve(solver, u0, H, W, dt, tau, sigma, iters, px, py, up);
         int band = 0;
         for (int k = 1; k <= K; ++k) {
             /* shift the window: (u_{k-1}, u_k) <- (u_{k-1}, u_k) of this k */
@@ -282,7 +352,7 @@ int orc_decompose(const float *f, int H, int W, int C, double dt, int K, int ite
                 memset(px, 0, n * sizeof(double));
                 memset(py, 0, n * sizeof(double));
             }
-            orc_rof(u0, H, W, dt, tau, iters, px, py, up); /* u_{k+1} */
+            rof_solve(solver, u0, H, W, dt, tau, sigma, iters, px, py, up); /* u_{k+1} */
             double tk = (double)k * dt;
             while (k > edges[band + 1])
                 ++band;
@@ -322,4 +392,13 @@ int orc_decompose(const float *f, int H, int W, int C, double dt, int K, int ite
     free(px);
     free(py);
     return 0;
+}
+
+/* orc_decompose_solver with Chambolle's dual fixed point. */
+int orc_decompose(const float *f, int H, int W, int C, double dt, int K, int iters,
+                  double tau, int warm, const int *edges, int nbands,
+                  double *bands, double *S, double *residual, double *report)
+{
+    return orc_decompose_solver(f, H, W, C, dt, K, iters, 0, tau, 0.0, warm, edges, nbands, bands, S,
+                                residual, report);
 }
