@@ -36,6 +36,10 @@ WORKLOAD = {
 # dual field is float32 in F32 and float64 in MIXED and F64, G is float32 in
 # F32 and MIXED and float64 in F64
 BYTES_PER_PIXEL_ITER = {"f32": 24, "mixed": 40, "f64": 48}
+# the same for the primal-dual kernel: read x, xbar, y (2) and the data u_k
+# (float64), write x, xbar, y (2); the iterates are float32 in F32, float64
+# otherwise
+PDHG_BYTES_PER_PIXEL_ITER = {"f32": 40, "mixed": 72, "f64": 72}
 # arithmetic type of the path, per precision mode
 DTYPE = {"f32": "f32", "mixed": "f64 (f32-seeded sqrt/rcp)", "f64": "f64"}
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
@@ -84,6 +88,44 @@ def cpu_baseline(f, wl):
     return {"value": mpix / sec, "unit": "MPix/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "one full decomposition of the same 512x512 workload (201 ROF solves x 300 "
                       "iterations), %.1f s" % sec}
+
+
+def pdhg_block(f, wl, edges, precision, steps):
+    """The same workload with the primal-dual inner solver (steps
+    1/sqrt(8)): time per decomposition, throughput and the roofline of its
+    tile kernel."""
+    import torch
+    from paper_2006_10004_amd import tvspec
+
+    def run(out=None):
+        return tvspec.tvspec_decompose_pdhg_dev(f, wl["dt"], wl["K"], wl["inner_iters"], edges,
+                                                precision=precision, out=out)
+
+    out = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run(out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tvspec.tvspec_timing_enable(True)
+    try:
+        run(out)
+        torch.cuda.synchronize()
+        t = tvspec.tvspec_timing_read()
+    finally:
+        tvspec.tvspec_timing_enable(False)
+    avg_ms = t["kernel_ms"] / t["launches"]
+    per_launch = PDHG_BYTES_PER_PIXEL_ITER[precision] * t["pixel_iters"] / t["launches"]
+    achieved = per_launch / (avg_ms / 1e3) / 1e9
+    st = out["stats"].cpu().numpy()
+    px = wl["H"] * wl["W"] * wl["C"]
+    return {"solver": "pdhg (Chambolle-Pock, tau = sigma = 1/sqrt(8))", "ms_per_step": ms,
+            "MPix_per_s": px / 1e6 / (ms / 1e3), "steps": steps,
+            "roofline": {"kernel": "k_pdhg_tile", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_ms * 1e3,
+                         "bytes_per_launch": per_launch, "launches_per_step": t["launches"]},
+            "report": {"recon_err": float(st[0]), "mean_err": float(st[1])}}
 
 
 def batch_throughput(n, precision):
@@ -246,6 +288,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate, requests/s (0 = 85%% of the burst's rate)")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--pdhg-steps", type=int, default=3,
+                    help="also time this many decompositions with the primal-dual solver (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -367,6 +411,10 @@ def main():
             "kernel_share_of_step": t["kernel_ms"] / ms_per_step,
         }
         print("bench: roofline pass done", file=sys.stderr, flush=True)
+
+    if args.pdhg_steps > 0:
+        rec["pdhg"] = pdhg_block(f, wl, edges, args.precision, args.pdhg_steps)
+        print("bench: primal-dual pass done", file=sys.stderr, flush=True)
 
     if args.batch_images > 0:
         rec["batch_64x64"] = batch_throughput(args.batch_images, args.precision)

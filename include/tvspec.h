@@ -82,6 +82,9 @@ extern "C" {
 #define TVSPEC_DEFAULT_PRECISION TVSPEC_PRECISION_MIXED
 
 #define TVSPEC_DEFAULT_TAU 0.248
+/* Default primal and dual steps of the primal-dual solver: 1/sqrt(8), so
+ * that tau sigma ||grad||^2 <= 1 (||grad||^2 <= 8). */
+#define TVSPEC_PDHG_DEFAULT_STEP 0.35355339059327373
 
 /* Number of doubles tvspec_decompose_dev writes to its stats buffer. */
 #define TVSPEC_NSTATS 4
@@ -147,6 +150,35 @@ TVSPEC_API int tvspec_decompose_dev(const float *f, int H, int W, int C, double 
                          int inner_iters, const int *band_edges, int n_bands, double *bands,
                          double *S, double *residual, double *stats, double tau, int warm_start,
                          int precision, int iters_per_launch, void *stream);
+
+/*
+ * Device entry point with the primal-dual ROF solver in place of Chambolle's
+ * dual fixed point: every implicit Euler step (Sec. 2.2, Eq. (8)) is solved by
+ * inner_iters iterations of Chambolle and Pock's first-order primal-dual
+ * algorithm (2011, Algorithm 1; the paper's GPU baseline is a primal-dual
+ * solver, Sec. 4.3) with operator grad, F = dt ||.||_{2,1}, G = 0.5 ||. - u_k||^2:
+ *     y    <- proj_{|y| <= dt}(y + sigma grad xbar)
+ *     x'   <- (x + tau div y + tau u_k) / (1 + tau)
+ *     xbar <- 2 x' - x,   x <- x'
+ * from x = xbar = u_k; u_{k+1} = x after the last iteration.  The spectral
+ * transform, bands, S, residual and report are those of
+ * tvspec_decompose_dev, computed from this flow.
+ *
+ *   tau, sigma  primal and dual steps, tau > 0, sigma > 0, 8 tau sigma <= 1;
+ *               tau = sigma = 0 selects TVSPEC_PDHG_DEFAULT_STEP for both
+ *   warm_start  0: every solve starts with y = 0; 1: y carries over from the
+ *               previous solve (x and xbar always start at u_k)
+ *   other arguments, layouts, ownership and ordering as
+ *   tvspec_decompose_dev (iters_per_launch: the same ranges and automatic
+ *   choice, for this solver's tile kernel).
+ *
+ * Errors: TVSPEC_EINVAL for bad steps and as tvspec_decompose_dev.
+ */
+TVSPEC_API int tvspec_decompose_pdhg_dev(const float *f, int H, int W, int C, double dt, int K,
+                                         int inner_iters, const int *band_edges, int n_bands,
+                                         double *bands, double *S, double *residual, double *stats,
+                                         double tau, double sigma, int warm_start, int precision,
+                                         int iters_per_launch, void *stream);
 
 /*
  * Batched device entry point: B images of the same size (H, W, C) and the

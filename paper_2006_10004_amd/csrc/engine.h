@@ -19,9 +19,14 @@
 
 namespace tvspec {
 
+// Inner ROF solvers.
+constexpr int kSolverChambolle = 0; // Chambolle's dual fixed point
+constexpr int kSolverPDHG = 1;      // Chambolle-Pock primal-dual
+
 struct SlotDesc {
     void *px[2], *py[2];  // dual field, ping-pong (state type of the mode)
-    void *gx, *gy;        // G = grad(g)/dt (type M of the mode)
+    void *gx, *gy;        // Chambolle: G = grad(g)/dt (type M of the mode)
+    void *x[2], *xb[2];   // PDHG: primal iterate and its extrapolation, ping-pong
     double *u[2];         // flow state; u_s lives in u[s % 2]
     double *dprev;        // D_{s-1}
     const float *f;       // [C][H][W]
@@ -49,14 +54,14 @@ size_t g_elem(int precision);
 // size, so partial sums are reproducible).
 int plane_blocks(int plane);
 
-// Device bytes of one slot's per-pixel engine buffers (dual field, G, u, D,
-// S and check partials), 256-byte aligned pieces.
-size_t slot_scratch_bytes(int precision, int H, int W, int C, int K);
+// Device bytes of one slot's per-pixel engine buffers (dual field, G or the
+// primal iterates, u, D, S and check partials), 256-byte aligned pieces.
+size_t slot_scratch_bytes(int precision, int solver, int H, int W, int C, int K);
 
 // Lay out those buffers in [base, base + slot_scratch_bytes) and fill the
 // slot's pointers to them and its K; f, the outputs, band_rows, nonfinite,
 // dt and nbands are set by the caller.
-void slot_carve(SlotDesc &d, char *base, int precision, int H, int W, int C, int K);
+void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W, int C, int K);
 
 // Round up to a multiple of 256 bytes.
 inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -72,6 +77,8 @@ struct StepConfig {
     int iters_per_launch; // 0: automatic
     int precision;
     int timed = 1;        // 0: never record benchmark timing (graph capture)
+    int solver = kSolverChambolle;
+    double sigma = 0.0;   // PDHG dual step (tau is its primal step)
 };
 
 // Tile-kernel launches per engine_step over a table of nslots slots (the

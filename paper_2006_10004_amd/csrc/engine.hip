@@ -170,9 +170,11 @@ __device__ __forceinline__ double block_max256(double v, double *sh)
 // ---------------------------------------------------------------------------
 // kernels
 
-// u_0 = f, G = grad f / dt, p = 0 (both buffers), bands = 0, for slot
-// first + blockIdx.y; counts non-finite inputs; starts the slot at step 0.
-template <typename S, typename M>
+// u_0 = f, G = grad f / dt (Chambolle only), p = 0 (both buffers), bands =
+// 0, for slot first + blockIdx.y; counts non-finite inputs; starts the slot
+// at step 0.  For PDHG p is its dual field y; its primal iterates are set at
+// the start of every solve.
+template <typename S, typename M, bool PD>
 __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots, int first, int H, int W, int C)
 {
     SlotDesc &sd = slots[first + blockIdx.y];
@@ -196,8 +198,10 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
         if (!isfinite(v))
             atomicAdd(sd.nonfinite, 1u);
         u[q] = (double)v;
-        gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
-        gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
+        if constexpr (!PD) {
+            gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
+            gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
+        }
         p0[q] = S(0);
         p1[q] = S(0);
         p2[q] = S(0);
@@ -430,6 +434,191 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
     }
 }
 
+// Projection factor of the PDHG dual step: min(1, lam / |z|) for |z|^2 = x,
+// so that z * factor is the projection of z onto the disc of radius lam
+// (factor 1 for z = 0).
+template <typename S, typename M> __device__ __forceinline__ S proj_factor(S x, S lam)
+{
+    if constexpr (std::is_same<S, M>::value) {
+        using A = Arith<S>;
+        const S f = lam * A::inv_(A::sqrt_(x)); // x = 0: lam * inf = inf
+        return f < S(1) ? f : S(1);
+    } else {
+        // float32 reciprocal square root estimate refined by one float64
+        // Newton step, as in the Chambolle update of this mode
+        S y = (S)__builtin_amdgcn_rsqf((float)x);
+        y = __builtin_fma(S(0.5) * y, __builtin_fma(-(x * y), y, S(1)), y);
+        const S f = lam * y;
+        return (x > S(1e-30) && f < S(1)) ? f : S(1);
+    }
+}
+
+// Temporally blocked Chambolle-Pock primal-dual iterations for the ROF
+// problem of the slot's current step (data g = u_k, weight lam = dt):
+//     y    <- proj_{|y| <= lam}(y + sigma grad xbar)
+//     x'   <- (x + tau div y + tau g) / (1 + tau)
+//     xbar <- 2 x' - x,   x <- x'
+// Same tiling, LDS ring, XCD-aware order and halo argument as
+// k_chambolle_tile (the new (x, xbar, y) of a pixel depends on the previous
+// iterate within one pixel).  LDS carries xbar for the gradient (right and
+// lower neighbours) and y for the divergence (left and upper neighbours).
+// With solve_start set (first launch of a solve) x and xbar start at g and
+// the dual field at zero (zero_y, cold start) or at the stored field (warm
+// start); otherwise all three are read from buffer `cur`.  Pixels outside
+// the image keep x = xbar = y = 0; grad xbar is masked to zero on the last
+// column / row, which keeps y_x = 0 there (y_y on the last row) and gives
+// the Neumann divergence.
+template <typename S, typename M, int BX, int BY, int TB, int NT>
+__global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ slots, int cur, int H, int W, int C,
+                                                 int ntx, int ntiles, S tau, S sigma, S inv1pt, int iters,
+                                                 int solve_start, int zero_y)
+{
+    const int slot = blockIdx.y / C;
+    const int chan = blockIdx.y - slot * C;
+    const SlotDesc &sd = slots[slot];
+    if (!sd.active)
+        return;
+    constexpr int RX = BX + 2 * TB;
+    constexpr int RY = BY + 2 * TB;
+    constexpr int RN = RX * RY;
+    constexpr int LX = RX + 2;
+    constexpr int LN = LX * (RY + 2);
+    constexpr int PPT = (RN + NT - 1) / NT;
+    __shared__ S s_xb[LN];
+    __shared__ S s_yx[LN];
+    __shared__ S s_yy[LN];
+
+    const size_t plane = (size_t)H * (size_t)W;
+    const size_t coff = (size_t)chan * plane;
+    const S lam = (S)sd.dt;
+    const double *__restrict__ g = sd.u[sd.k_cur & 1] + coff;
+    const S *__restrict__ xi = (const S *)sd.x[cur] + coff;
+    const S *__restrict__ xbi = (const S *)sd.xb[cur] + coff;
+    const S *__restrict__ yxi = (const S *)sd.px[cur] + coff;
+    const S *__restrict__ yyi = (const S *)sd.py[cur] + coff;
+    S *__restrict__ xo = (S *)sd.x[1 - cur] + coff;
+    S *__restrict__ xbo = (S *)sd.xb[1 - cur] + coff;
+    S *__restrict__ yxo = (S *)sd.px[1 - cur] + coff;
+    S *__restrict__ yyo = (S *)sd.py[1 - cur] + coff;
+
+    const int b = blockIdx.x;
+    const int L = ((ntiles & 7) == 0) ? (b & 7) * (ntiles >> 3) + (b >> 3) : b;
+    const int ty = L / ntx;
+    const int tx = L - ty * ntx;
+    const int oy = ty * BY - TB;
+    const int ox = tx * BX - TB;
+
+    for (int e = threadIdx.x; e < 2 * LX + 2 * RY; e += NT) {
+        int li;
+        if (e < LX)
+            li = e;
+        else if (e < 2 * LX)
+            li = (RY + 1) * LX + (e - LX);
+        else if (e < 2 * LX + RY)
+            li = (e - 2 * LX + 1) * LX;
+        else
+            li = (e - 2 * LX - RY + 1) * LX + LX - 1;
+        s_xb[li] = S(0);
+        s_yx[li] = S(0);
+        s_yy[li] = S(0);
+    }
+
+    S x[PPT], xb[PPT], yx[PPT], yy[PPT], gg[PPT], mx[PPT], my[PPT];
+    int li[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int idx = threadIdx.x + m * NT;
+        S vx = S(0), vxb = S(0), vyx = S(0), vyy = S(0), vg = S(0);
+        bool ax_live = false, ay_live = false;
+        int l = 0;
+        if (idx < RN) {
+            const int ri = idx / RX;
+            const int rj = idx - ri * RX;
+            const int gi = oy + ri;
+            const int gj = ox + rj;
+            l = (ri + 1) * LX + (rj + 1);
+            if (gi >= 0 && gi < H && gj >= 0 && gj < W) {
+                const size_t q = (size_t)gi * W + gj;
+                vg = (S)g[q];
+                if (solve_start) {
+                    vx = vg;
+                    vxb = vg;
+                } else {
+                    vx = xi[q];
+                    vxb = xbi[q];
+                }
+                if (!zero_y) {
+                    vyx = yxi[q];
+                    vyy = yyi[q];
+                }
+                ax_live = gj < W - 1;
+                ay_live = gi < H - 1;
+            }
+            s_xb[l] = vxb;
+        }
+        li[m] = l;
+        x[m] = vx;
+        xb[m] = vxb;
+        yx[m] = vyx;
+        yy[m] = vyy;
+        gg[m] = vg;
+        mx[m] = ax_live ? S(1) : S(0);
+        my[m] = ay_live ? S(1) : S(0);
+    }
+    __syncthreads();
+
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+                const int l = li[m];
+                const S ax = (s_xb[l + 1] - xb[m]) * mx[m];
+                const S ay = (s_xb[l + LX] - xb[m]) * my[m];
+                const S zx = Arith<S>::fma_(sigma, ax, yx[m]);
+                const S zy = Arith<S>::fma_(sigma, ay, yy[m]);
+                const S f = proj_factor<S, M>(zx * zx + zy * zy, lam);
+                yx[m] = zx * f;
+                yy[m] = zy * f;
+                s_yx[l] = yx[m];
+                s_yy[l] = yy[m];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+                const int l = li[m];
+                const S d = (yx[m] - s_yx[l - 1]) + (yy[m] - s_yy[l - LX]);
+                const S t = Arith<S>::fma_(tau, gg[m], Arith<S>::fma_(tau, d, x[m]));
+                const S xn = t * inv1pt;
+                const S xbn = xn + (xn - x[m]);
+                x[m] = xn;
+                xb[m] = xbn;
+                s_xb[l] = xbn;
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int idx = threadIdx.x + m * NT;
+        if (idx < RN) {
+            const int ri = idx / RX;
+            const int rj = idx - ri * RX;
+            const int gi = oy + ri;
+            const int gj = ox + rj;
+            if (ri >= TB && ri < TB + BY && rj >= TB && rj < TB + BX && gi < H && gj < W) {
+                const size_t q = (size_t)gi * W + gj;
+                xo[q] = x[m];
+                xbo[q] = xb[m];
+                yxo[q] = yx[m];
+                yyo[q] = yy[m];
+            }
+        }
+    }
+}
+
 // div p at pixel q = (i, j) of one channel plane, in float64 from the stored
 // dual field (zero outside the image).
 template <typename S>
@@ -443,17 +632,21 @@ __device__ __forceinline__ double div_p(const S *__restrict__ px, const S *__res
 
 // Outer step k = k_cur of every active slot, fused with the spectral
 // transform.  Grid: (nblk, slots * C), nblk fixed per image size so partial
-// sums are reproducible.  The final dual field of the solve is in buffer cur.
-//   D_k     = dt div p                     (u_k - u_{k+1})
-//   u_{k+1} = u_k - D_k                    (u[(k+1) % 2])
+// sums are reproducible.  The final iterate of the solve is in buffer cur.
+//   Chambolle (PD = false):
+//     D_k     = dt div p                   (u_k - u_{k+1})
+//     u_{k+1} = u_k - D_k                  (u[(k+1) % 2])
+//   PDHG (PD = true):
+//     u_{k+1} = x, the solve's primal iterate;  D_k = u_k - u_{k+1}
+//   both:
 //   k >= 1: phi_k dt = k (D_{k-1} - D_k)   added to the band holding k
 //           spart  <- block sum of |D_{k-1} - D_k|   (S(t_k) = k/dt * total)
 //   k == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t)
-//   G       = grad(u_{k+1}) / dt           (data term of the next solve; the
-//             right and lower neighbours' u_{k+1} are recomputed here with
-//             the same operations their own threads use, so they match bit
-//             for bit)
-template <typename S, typename M>
+//   G       = grad(u_{k+1}) / dt           (Chambolle only: data term of the
+//             next solve; the right and lower neighbours' u_{k+1} are
+//             recomputed here with the same operations their own threads
+//             use, so they match bit for bit)
+template <typename S, typename M, bool PD>
 __global__ __launch_bounds__(kThreads) void k_flow_step(const SlotDesc *__restrict__ slots, int cur, int H, int W,
                                                         int C)
 {
@@ -484,9 +677,15 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const SlotDesc *__restri
     for (int q = blockIdx.x * kThreads + threadIdx.x; q < plane; q += gridDim.x * kThreads) {
         const int i = q / W;
         const int j = q - i * W;
-        const double D = dt * div_p(px, py, q, i, j, W);
         const double uo = uin[q];
-        const double un = uo - D;
+        double D, un;
+        if constexpr (PD) {
+            un = (double)((const S *)sd.x[cur] + coff)[q]; // the solve's primal iterate
+            D = uo - un;
+        } else {
+            D = dt * div_p(px, py, q, i, j, W);
+            un = uo - D;
+        }
         if (k >= 1) {
             const double dl = dprev[q] - D;
             band[q] += kd * dl;
@@ -496,17 +695,19 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const SlotDesc *__restri
             resid[q] = uo + (double)K * D;
         uout[q] = un;
         dprev[q] = D;
-        if (j < W - 1) {
-            const double unr = uin[q + 1] - dt * div_p(px, py, q + 1, i, j + 1, W);
-            gx[q] = (M)((unr - un) / dt);
-        } else {
-            gx[q] = M(0);
-        }
-        if (i < H - 1) {
-            const double und = uin[q + W] - dt * div_p(px, py, q + W, i + 1, j, W);
-            gy[q] = (M)((und - un) / dt);
-        } else {
-            gy[q] = M(0);
+        if constexpr (!PD) {
+            if (j < W - 1) {
+                const double unr = uin[q + 1] - dt * div_p(px, py, q + 1, i, j + 1, W);
+                gx[q] = (M)((unr - un) / dt);
+            } else {
+                gx[q] = M(0);
+            }
+            if (i < H - 1) {
+                const double und = uin[q + W] - dt * div_p(px, py, q + W, i + 1, j, W);
+                gy[q] = (M)((und - un) / dt);
+            } else {
+                gy[q] = M(0);
+            }
         }
     }
     if (k >= 1) {
@@ -640,6 +841,23 @@ using TileKernel = void (*)(const SlotDesc *, int, int, int, int, int, int, S, i
 // the (32+2TB)^2 region, which are sized by the dual-field type S).
 template <typename S> constexpr int max_tb() { return std::is_same<S, float>::value ? 16 : 8; }
 
+template <typename S, typename M>
+using PdhgKernel = void (*)(const SlotDesc *, int, int, int, int, int, int, S, S, S, int, int, int);
+
+// Smallest compiled halo width >= t of the primal-dual kernel.
+template <typename S, typename M> PdhgKernel<S, M> pdhg_kernel(int t, int *tb)
+{
+    if (t <= 1) { *tb = 1; return k_pdhg_tile<S, M, kTileX, kTileY, 1, kTileThreads>; }
+    if (t <= 2) { *tb = 2; return k_pdhg_tile<S, M, kTileX, kTileY, 2, kTileThreads>; }
+    if (t <= 4) { *tb = 4; return k_pdhg_tile<S, M, kTileX, kTileY, 4, kTileThreads>; }
+    if (t <= 5) { *tb = 5; return k_pdhg_tile<S, M, kTileX, kTileY, 5, kTileThreads>; }
+    if constexpr (max_tb<S>() >= 16) {
+        if (t > 8) { *tb = 16; return k_pdhg_tile<S, M, kTileX, kTileY, 16, kTileThreads>; }
+    }
+    *tb = 8;
+    return k_pdhg_tile<S, M, kTileX, kTileY, 8, kTileThreads>;
+}
+
 // Smallest compiled halo width >= t.
 template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
@@ -736,8 +954,12 @@ template <typename S, typename M> int init_impl(const StepConfig &cfg, SlotDesc 
                                                 hipStream_t st)
 {
     const size_t n = (size_t)cfg.C * cfg.H * cfg.W;
-    hipLaunchKernelGGL((k_init<S, M>), dim3(blocks_for(n, 1024), count), dim3(kThreads), 0, st, d_slots, first,
-                       cfg.H, cfg.W, cfg.C);
+    if (cfg.solver == kSolverPDHG)
+        hipLaunchKernelGGL((k_init<S, M, true>), dim3(blocks_for(n, 1024), count), dim3(kThreads), 0, st, d_slots,
+                           first, cfg.H, cfg.W, cfg.C);
+    else
+        hipLaunchKernelGGL((k_init<S, M, false>), dim3(blocks_for(n, 1024), count), dim3(kThreads), 0, st, d_slots,
+                           first, cfg.H, cfg.W, cfg.C);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -749,10 +971,16 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
     const int ntx = (cfg.W + kTileX - 1) / kTileX;
     const int nty = (cfg.H + kTileY - 1) / kTileY;
     const int ntiles = ntx * nty;
+    const bool pd = cfg.solver == kSolverPDHG;
     int tb = 0;
     const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
                                               : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C);
-    TileKernel<S, M> kt = tile_kernel<S, M>(want, &tb);
+    TileKernel<S, M> kt = nullptr;
+    PdhgKernel<S, M> kp = nullptr;
+    if (pd)
+        kp = pdhg_kernel<S, M>(want, &tb);
+    else
+        kt = tile_kernel<S, M>(want, &tb);
     const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
     int cur = *parity;
 
@@ -768,8 +996,13 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
         // cold start: the first launch of a solve starts from p = 0
         const int zero_in = (!cfg.warm && done == 0) ? 1 : 0;
         const int it = (cfg.iters - done) < per_launch ? (cfg.iters - done) : per_launch;
-        hipLaunchKernelGGL(kt, dim3(ntiles, nslots * cfg.C), dim3(kTileThreads), 0, st, d_slots, cur, cfg.H, cfg.W,
-                           cfg.C, ntx, ntiles, (S)cfg.tau, it, zero_in);
+        if (pd)
+            hipLaunchKernelGGL(kp, dim3(ntiles, nslots * cfg.C), dim3(kTileThreads), 0, st, d_slots, cur, cfg.H,
+                               cfg.W, cfg.C, ntx, ntiles, (S)cfg.tau, (S)cfg.sigma, (S)(1.0 / (1.0 + cfg.tau)), it,
+                               done == 0 ? 1 : 0, zero_in);
+        else
+            hipLaunchKernelGGL(kt, dim3(ntiles, nslots * cfg.C), dim3(kTileThreads), 0, st, d_slots, cur, cfg.H,
+                               cfg.W, cfg.C, ntx, ntiles, (S)cfg.tau, it, zero_in);
         if (timed) {
             ++g_timing.launches;
             g_timing.pixel_iters += live_planes * plane * it;
@@ -779,8 +1012,12 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
     }
     if (timed)
         HIP_TRY(hipEventRecord(e1, st));
-    hipLaunchKernelGGL((k_flow_step<S, M>), dim3(plane_blocks(plane), nslots * cfg.C), dim3(kThreads), 0, st,
-                       d_slots, cur, cfg.H, cfg.W, cfg.C);
+    if (pd)
+        hipLaunchKernelGGL((k_flow_step<S, M, true>), dim3(plane_blocks(plane), nslots * cfg.C), dim3(kThreads), 0,
+                           st, d_slots, cur, cfg.H, cfg.W, cfg.C);
+    else
+        hipLaunchKernelGGL((k_flow_step<S, M, false>), dim3(plane_blocks(plane), nslots * cfg.C), dim3(kThreads), 0,
+                           st, d_slots, cur, cfg.H, cfg.W, cfg.C);
     hipLaunchKernelGGL(k_advance, dim3((nslots + kThreads - 1) / kThreads), dim3(kThreads), 0, st, d_slots, nslots);
     HIP_TRY(hipGetLastError());
     *parity = cur;
@@ -794,18 +1031,20 @@ size_t g_elem(int precision) { return precision == TVSPEC_PRECISION_F64 ? 8 : 4;
 
 int plane_blocks(int plane) { return blocks_for((size_t)plane, 1024); }
 
-size_t slot_scratch_bytes(int precision, int H, int W, int C, int K)
+size_t slot_scratch_bytes(int precision, int solver, int H, int W, int C, int K)
 {
     const size_t n = (size_t)C * H * W;
     const size_t nblk = (size_t)plane_blocks(H * W);
+    const size_t solver_bytes = solver == kSolverPDHG ? 4 * align256(n * state_elem(precision)) // x[2], xb[2]
+                                                      : 2 * align256(n * g_elem(precision));     // gx, gy
     return 4 * align256(n * state_elem(precision))     // px[2], py[2]
-           + 2 * align256(n * g_elem(precision))        // gx, gy
+           + solver_bytes
            + 3 * align256(n * sizeof(double))           // u[2], dprev
            + align256((size_t)K * C * nblk * sizeof(double)) // spart
            + align256((size_t)C * nblk * 3 * sizeof(double)); // rpart
 }
 
-void slot_carve(SlotDesc &d, char *base, int precision, int H, int W, int C, int K)
+void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W, int C, int K)
 {
     const size_t n = (size_t)C * H * W;
     const size_t nblk = (size_t)plane_blocks(H * W);
@@ -819,8 +1058,17 @@ void slot_carve(SlotDesc &d, char *base, int precision, int H, int W, int C, int
     d.px[1] = take(n * state_elem(precision));
     d.py[0] = take(n * state_elem(precision));
     d.py[1] = take(n * state_elem(precision));
-    d.gx = take(n * g_elem(precision));
-    d.gy = take(n * g_elem(precision));
+    if (solver == kSolverPDHG) {
+        d.gx = d.gy = nullptr;
+        d.x[0] = take(n * state_elem(precision));
+        d.x[1] = take(n * state_elem(precision));
+        d.xb[0] = take(n * state_elem(precision));
+        d.xb[1] = take(n * state_elem(precision));
+    } else {
+        d.gx = take(n * g_elem(precision));
+        d.gy = take(n * g_elem(precision));
+        d.x[0] = d.x[1] = d.xb[0] = d.xb[1] = nullptr;
+    }
     d.u[0] = (double *)take(n * sizeof(double));
     d.u[1] = (double *)take(n * sizeof(double));
     d.dprev = (double *)take(n * sizeof(double));

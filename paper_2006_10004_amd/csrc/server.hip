@@ -282,7 +282,7 @@ int try_admit(tvspec_server *s, Request *q, bool *admitted)
     char *base = s->pool + off;
     SlotDesc d;
     std::memset(&d, 0, sizeof(d));
-    slot_carve(d, base, s->precision, b.H, b.W, b.C, K);
+    slot_carve(d, base, s->precision, kSolverChambolle, b.H, b.W, b.C, K);
     int *d_rows = (int *)(base + q->scratch);
     unsigned int *d_nf = (unsigned int *)(base + q->scratch + align256((size_t)(K + 1) * sizeof(int)));
     d.band_rows = d_rows;
@@ -629,7 +629,7 @@ extern "C" int tvspec_submit(tvspec_server *srv, const tvspec_request *req, unsi
     q->r = r;
     q->edges.assign(r.band_edges, r.band_edges + r.n_bands + 1);
     q->r.band_edges = nullptr;
-    q->scratch = slot_scratch_bytes(srv->precision, r.H, r.W, r.C, r.K);
+    q->scratch = slot_scratch_bytes(srv->precision, kSolverChambolle, r.H, r.W, r.C, r.K);
     q->footprint = q->scratch + align256((size_t)(r.K + 1) * sizeof(int)) + 256;
     if (q->footprint > srv->budget)
         return fail(TVSPEC_EBUSY, "request needs " + std::to_string(q->footprint) +

@@ -118,6 +118,8 @@ struct Batch {
     double tau;
     int warm, ipl, precision;
     hipStream_t st;
+    int solver = kSolverChambolle;
+    double sigma = 0.0;
 };
 
 int run_batch(const Batch &a)
@@ -134,7 +136,7 @@ int run_batch(const Batch &a)
     for (int b = 0; b < a.B; ++b) {
         Kmax = a.K[b] > Kmax ? a.K[b] : Kmax;
         rows_n += (size_t)a.K[b] + 1;
-        slots_bytes += slot_scratch_bytes(a.precision, a.H, a.W, a.C, a.K[b]);
+        slots_bytes += slot_scratch_bytes(a.precision, a.solver, a.H, a.W, a.C, a.K[b]);
     }
     const size_t table_bytes = align256((size_t)a.B * sizeof(SlotDesc));
     const size_t rows_bytes = align256(rows_n * sizeof(int));
@@ -154,8 +156,8 @@ int run_batch(const Batch &a)
     for (int b = 0, e0 = 0; b < a.B; ++b) {
         SlotDesc d;
         std::memset(&d, 0, sizeof(d));
-        slot_carve(d, slot_base, a.precision, a.H, a.W, a.C, a.K[b]);
-        slot_base += slot_scratch_bytes(a.precision, a.H, a.W, a.C, a.K[b]);
+        slot_carve(d, slot_base, a.precision, a.solver, a.H, a.W, a.C, a.K[b]);
+        slot_base += slot_scratch_bytes(a.precision, a.solver, a.H, a.W, a.C, a.K[b]);
         band_rows_of(a.edges + e0, a.nb[b], h_rows + row0);
         d.band_rows = d_rows + row0;
         d.nonfinite = d_nf + b;
@@ -178,7 +180,9 @@ int run_batch(const Batch &a)
     sg.pending = true;
     HIP_TRY(hipMemsetAsync(d_nf, 0, (size_t)a.B * sizeof(unsigned int), a.st));
 
-    const StepConfig cfg{a.H, a.W, a.C, a.iters, a.tau, a.warm, a.ipl, a.precision};
+    StepConfig cfg{a.H, a.W, a.C, a.iters, a.tau, a.warm, a.ipl, a.precision};
+    cfg.solver = a.solver;
+    cfg.sigma = a.sigma;
     TVSPEC_TRY(engine_init(cfg, d_table, 0, a.B, a.st));
     int parity = 0;
     for (int s = 0; s <= Kmax; ++s) {
@@ -334,6 +338,48 @@ extern "C" int tvspec_decompose_dev(const float *f, int H, int W, int C, double 
     a.ipl = iters_per_launch;
     a.precision = precision;
     a.st = (hipStream_t)stream;
+    return run_batch(a);
+}
+
+extern "C" int tvspec_decompose_pdhg_dev(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
+                                         const int *band_edges, int n_bands, double *bands, double *S,
+                                         double *residual, double *stats, double tau, double sigma, int warm_start,
+                                         int precision, int iters_per_launch, void *stream)
+{
+    g_last_error.clear();
+    if (!f || !band_edges || !bands || !S || !residual || !stats)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (tau == 0.0 && sigma == 0.0)
+        tau = sigma = TVSPEC_PDHG_DEFAULT_STEP;
+    if (!std::isfinite(tau) || !std::isfinite(sigma) || !(tau > 0.0) || !(sigma > 0.0) ||
+        tau * sigma * 8.0 > 1.0 + 1e-12)
+        return fail(TVSPEC_EINVAL, "PDHG steps need tau > 0, sigma > 0 and 8 tau sigma <= 1");
+    TVSPEC_TRY(validate_shape(1, H, W, C, inner_iters));
+    TVSPEC_TRY(validate_image(dt, K, band_edges, n_bands));
+    TVSPEC_TRY(validate_opts(TVSPEC_DEFAULT_TAU, warm_start, precision, iters_per_launch));
+    std::lock_guard<std::mutex> lock(g_mu);
+    Batch a;
+    a.f = f;
+    a.B = 1;
+    a.H = H;
+    a.W = W;
+    a.C = C;
+    a.iters = inner_iters;
+    a.dt = &dt;
+    a.K = &K;
+    a.edges = band_edges;
+    a.nb = &n_bands;
+    a.bands = bands;
+    a.S = S;
+    a.res = residual;
+    a.stats = stats;
+    a.tau = tau;
+    a.warm = warm_start;
+    a.ipl = iters_per_launch;
+    a.precision = precision;
+    a.st = (hipStream_t)stream;
+    a.solver = kSolverPDHG;
+    a.sigma = sigma;
     return run_batch(a);
 }
 

@@ -32,12 +32,14 @@ TVSPEC_PRECISION_MIXED = 2
 PRECISIONS = {"f32": TVSPEC_PRECISION_F32, "f64": TVSPEC_PRECISION_F64, "mixed": TVSPEC_PRECISION_MIXED}
 DEFAULT_PRECISION = "mixed"
 TVSPEC_DEFAULT_TAU = 0.248
+TVSPEC_PDHG_DEFAULT_STEP = 0.35355339059327373
 TVSPEC_NSTATS = 4
 
 EXPORTS = (
     "tvspec_decompose",
     "tvspec_decompose_dev",
     "tvspec_decompose_batch_dev",
+    "tvspec_decompose_pdhg_dev",
     "tvspec_dyadic_edges",
     "tvspec_timing_enable",
     "tvspec_timing_read",
@@ -91,6 +93,8 @@ def _load():
     lib.tvspec_decompose_batch_dev.argtypes = [vp, i, i, i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, d, i, i, i,
                                                vp]
     lib.tvspec_decompose_batch_dev.restype = i
+    lib.tvspec_decompose_pdhg_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, d, i, i, i, vp]
+    lib.tvspec_decompose_pdhg_dev.restype = i
     lib.tvspec_dyadic_edges.argtypes = [i, i, vp]
     lib.tvspec_dyadic_edges.restype = i
     lib.tvspec_timing_enable.argtypes = [i]
@@ -232,6 +236,34 @@ def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, b
             out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
             out["stats"].data_ptr(), float(tau), 1 if warm_start else 0, prec,
             int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def tvspec_decompose_pdhg_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges,
+                              tau: float = 0.0, sigma: float = 0.0, warm_start: bool = False,
+                              precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
+                              stream: torch.cuda.Stream | None = None, out: dict | None = None):
+    """As tvspec_decompose_dev, with the Chambolle-Pock primal-dual ROF solver
+    (primal step tau, dual step sigma; 0, 0 = 1/sqrt(8) each)."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32:
+        raise TypeError("f must be a float32 GPU tensor")
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    if f.dim() != 3:
+        raise ValueError("f must be (C,H,W) or (H,W)")
+    f = f.contiguous()
+    C, H, W = f.shape
+    e = _edges_array(band_edges)
+    B = e.size - 1
+    dev = f.device
+    out = _outputs(out, B, C, H, W, int(K), dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(_lib.tvspec_decompose_pdhg_dev(
+            f.data_ptr(), H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
+            out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
+            out["stats"].data_ptr(), float(tau), float(sigma), 1 if warm_start else 0,
+            PRECISIONS[precision], int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
     return out
 
 

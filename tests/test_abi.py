@@ -119,6 +119,23 @@ def test_device_entry_validation_options():
     assert rc == -1
 
 
+def test_pdhg_entry_validation():
+    """The primal-dual entry point checks its steps before any device work."""
+    lib = ctypes.CDLL(LIB)
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.tvspec_decompose_pdhg_dev.argtypes = [vp, ci, ci, ci, cd, ci, ci, vp, ci, vp, vp, vp, vp, cd, cd, ci, ci,
+                                              ci, vp]
+    e = np.array([0, 4], dtype=np.int32)
+    fake = vp(0x1000)  # never dereferenced: validation fails first
+    for tau, sigma in [(0.5, 0.5), (-0.1, 0.2), (0.2, -0.1), (0.0, 0.3), (float("inf"), 0.1)]:
+        rc = lib.tvspec_decompose_pdhg_dev(fake, 8, 8, 1, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake, fake,
+                                           fake, tau, sigma, 0, 2, 0, None)
+        assert rc == -1, (tau, sigma)
+    rc = lib.tvspec_decompose_pdhg_dev(fake, 8, 8, 1, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake, fake,
+                                       fake, 0.0, 0.0, 0, 7, 0, None)
+    assert rc == -1  # bad precision
+
+
 def test_server_entry_validation():
     """Server entry points reject bad options and null handles before any
     device work."""
