@@ -1,0 +1,1203 @@
+// tvspec_nn: the learned surrogate (include/tvspec_nn.h) on gfx950.
+//
+// Convolutions are implicit GEMMs on the matrix cores.  With pixels p and
+// the reduction index k = tap * Cin + c (tap = 3 dy + dx), a 3x3 "same"
+// convolution is Y[p][o] = sum_k A[p][k] Wt[o][k] with A[p][k] = X[p +
+// (dy-1, dx-1)][c] (zero outside the image).  Channels-last storage makes
+// the 8 consecutive k of one MFMA operand lane 8 consecutive channels of
+// one pixel at one tap, i.e. one 16-byte load, as long as Cin is a multiple
+// of 8.  v_mfma_f32_16x16x32_bf16 (gfx950) lane layout: A row l % 16 with k
+// 8(l / 16) .. +7, B column l % 16 with the same k, result column l % 16,
+// rows 4(l / 16) .. +3.
+//
+//   k_conv3x3      forward (and the input gradient, on flipped, transposed
+//                  weights): a workgroup of 4 waves covers 128 pixels x 64
+//                  output channels; each wave 32 pixels x 64 channels as
+//                  2 x 4 MFMA tiles, operands loaded straight from global
+//                  memory (the 9 taps re-read neighbouring pixels through the
+//                  caches); bias, ReLU or a ReLU mask fused in the epilogue.
+//   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
+//                  64 output channels x 64 values of k over a range of
+//                  pixels, stages 64-pixel chunks of dY and of the shifted X
+//                  in LDS transposed (k-major), so MFMA operands are 16-byte
+//                  LDS reads; per-range partial sums are added in a fixed
+//                  order by k_reduce_rows (deterministic).
+//   the rest       packing, 2x2 max-pooling, nearest upsampling with skip
+//                  concatenation, their gradients (ReLU masks fused), the
+//                  normalised MSE loss and its gradient, Adam.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "tvspec_nn.h"
+
+namespace tvspec {
+namespace nn {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        z[j] = (__bf16)0.0f;
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+// convolution (forward and input gradient)
+
+// Y[p][o] = epilogue(sum_k A[p][k] Wt[o][k]), Wt [Cout][9][Cin].
+// Epilogue: + bias[o] (bias != nullptr), max(., 0) (relu), zero where
+// mask[p][o] <= 0 (mask != nullptr); stored as bf16 or f32.
+template <bool F32OUT>
+__global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
+                                                const float *__restrict__ bias, const __bf16 *__restrict__ mask,
+                                                void *__restrict__ Y, int B, int H, int W, int Cin, int Cout,
+                                                int relu)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r16 = lane & 15;
+    const int g = lane >> 4;
+    const long long P = (long long)B * H * W;
+    const long long p0 = (long long)blockIdx.x * 128 + wave * 32;
+    const int co0 = blockIdx.y * 64;
+    const int K = 9 * Cin;
+
+    int pb[2], py[2], px[2];
+    bool pv[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const long long p = p0 + r * 16 + r16;
+        pv[r] = p < P;
+        const long long q = pv[r] ? p : 0;
+        pb[r] = (int)(q / ((long long)H * W));
+        const int rem = (int)(q - (long long)pb[r] * H * W);
+        py[r] = rem / W;
+        px[r] = rem - py[r] * W;
+    }
+    const __bf16 *wrow[4];
+    bool wv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int co = co0 + c * 16 + r16;
+        wv[c] = co < Cout;
+        wrow[c] = Wt + (size_t)(wv[c] ? co : 0) * K;
+    }
+
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // this lane's k = ks * 32 + 8 g: tap and channel, advanced incrementally
+    int tap = (8 * g) / Cin;
+    int ch = 8 * g - tap * Cin;
+    const int nks = (K + 31) / 32;
+    for (int ks = 0; ks < nks; ++ks) {
+        const int k = ks * 32 + 8 * g;
+        bf16x8 a[2], b[4];
+        if (k < K) {
+            const int dy = tap / 3 - 1;
+            const int dx = tap - (tap / 3) * 3 - 1;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int yy = py[r] + dy;
+                const int xx = px[r] + dx;
+                if (pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    a[r] = *(const bf16x8 *)(X + ((size_t)((size_t)pb[r] * H + yy) * W + xx) * Cin + ch);
+                else
+                    a[r] = zero8();
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                b[c] = wv[c] ? *(const bf16x8 *)(wrow[c] + k) : zero8();
+        } else {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                a[r] = zero8();
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                b[c] = zero8();
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+        ch += 32;
+        while (ch >= Cin) {
+            ch -= Cin;
+            ++tap;
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int co = co0 + c * 16 + r16;
+            if (co >= Cout)
+                continue;
+            const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long p = p0 + r * 16 + 4 * g + i;
+                if (p >= P)
+                    continue;
+                float v = acc[r][c][i] + bv;
+                if (relu)
+                    v = v > 0.f ? v : 0.f;
+                if (mask && !((float)mask[(size_t)p * Cout + co] > 0.f))
+                    v = 0.f;
+                if constexpr (F32OUT)
+                    ((float *)Y)[(size_t)p * Cout + co] = v;
+                else
+                    ((__bf16 *)Y)[(size_t)p * Cout + co] = (__bf16)v;
+            }
+        }
+    }
+}
+
+// Weights for the input gradient: Wd[c][tap][o] = W[o][8 - tap][c].
+__global__ __launch_bounds__(kT) void k_flip_transpose(const __bf16 *__restrict__ W, __bf16 *__restrict__ Wd,
+                                                       int Cout, int Cin)
+{
+    const size_t n = (size_t)Cout * 9 * Cin;
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n; q += (size_t)gridDim.x * kT) {
+        const int c = (int)(q % Cin);
+        const int tap = (int)((q / Cin) % 9);
+        const int o = (int)(q / ((size_t)9 * Cin));
+        Wd[((size_t)c * 9 + (8 - tap)) * Cout + o] = W[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient
+
+constexpr int kWChunk = 64;             // pixels per LDS stage
+constexpr int kWPitch = kWChunk + 8;    // LDS row pitch (elements), 16-byte aligned rows
+
+// part[s][o][k] = sum over pixels of range s of dY[p][o] * A[p][k], for the
+// 64 x 64 tile (o0, k0) of (Cout, 9 Cin).  Range s covers chunks
+// [s * cps, (s + 1) * cps) of kWChunk pixels.
+__global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
+                                              float *__restrict__ part, int B, int H, int W, int Cin, int Cout,
+                                              int cps)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sA[64 * kWPitch]; // [o][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sB[64 * kWPitch]; // [k][pixel]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r16 = lane & 15;
+    const int g = lane >> 4;
+    const int K = 9 * Cin;
+    const int k0 = blockIdx.x * 64;
+    const int o0 = blockIdx.y * 64;
+    const int s = blockIdx.z;
+    const long long P = (long long)B * H * W;
+    const long long HW = (long long)H * W;
+
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // staging roles: thread t handles pixel t / 8 (+32) and group t % 8 of 8
+    // channels (dY) or 8 values of k (X)
+    const int sp = threadIdx.x >> 3;
+    const int sg = threadIdx.x & 7;
+    const int ko = k0 + sg * 8;       // this thread's 8 values of k
+    const bool kval = ko < K;
+    const int tap = kval ? ko / Cin : 0;
+    const int ch = kval ? ko - tap * Cin : 0;
+    const int dy = tap / 3 - 1;
+    const int dx = tap - (tap / 3) * 3 - 1;
+    const int oo = o0 + sg * 8;
+    const bool oval = oo < Cout;
+
+    for (int chunk = 0; chunk < cps; ++chunk) {
+        const long long pbase = ((long long)s * cps + chunk) * kWChunk;
+        if (pbase >= P)
+            break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int pl = sp + 32 * h;
+            const long long p = pbase + pl;
+            bf16x8 va = zero8(), vb = zero8();
+            if (p < P) {
+                if (oval)
+                    va = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
+                if (kval) {
+                    const int b = (int)(p / HW);
+                    const int rem = (int)(p - (long long)b * HW);
+                    const int yy = rem / W + dy;
+                    const int xx = rem - (rem / W) * W + dx;
+                    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                        vb = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sA[(sg * 8 + j) * kWPitch + pl] = va[j];
+                sB[(sg * 8 + j) * kWPitch + pl] = vb[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kWChunk; kk += 32) {
+            const bf16x8 a = *(const bf16x8 *)(sA + (wave * 16 + r16) * kWPitch + kk + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bf16x8 b = *(const bf16x8 *)(sB + (j * 16 + r16) * kWPitch + kk + 8 * g);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float *out = part + (size_t)s * Cout * K;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = k0 + j * 16 + r16;
+        if (k >= K)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = o0 + wave * 16 + 4 * g + i;
+            if (o < Cout)
+                out[(size_t)o * K + k] = acc[j][i];
+        }
+    }
+}
+
+// out[q] = sum_s part[s * n + q], s = 0 .. ns-1 in order.
+__global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ part, int ns, size_t n,
+                                                    float *__restrict__ out)
+{
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n; q += (size_t)gridDim.x * kT) {
+        float a = 0.f;
+        for (int s = 0; s < ns; ++s)
+            a += part[(size_t)s * n + q];
+        out[q] = a;
+    }
+}
+
+// part[s][o] = sum of dY[p][o] over the pixels of range s (cps pixels each).
+__global__ __launch_bounds__(kT) void k_bias_partial(const __bf16 *__restrict__ dY, long long P, int Cout,
+                                                     long long cps, float *__restrict__ part)
+{
+    const int s = blockIdx.y;
+    const long long pa = s * cps;
+    const long long pe = pa + cps < P ? pa + cps : P;
+    for (int o = blockIdx.x * kT + threadIdx.x; o < Cout; o += gridDim.x * kT) {
+        float a = 0.f;
+        for (long long p = pa; p < pe; ++p)
+            a += (float)dY[(size_t)p * Cout + o];
+        part[(size_t)s * Cout + o] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layout, pooling, upsampling
+
+// f [B][3][H][W] float -> x [B][H][W][8] bf16, channels 3..7 zero.
+__global__ __launch_bounds__(kT) void k_pack_input(const float *__restrict__ f, __bf16 *__restrict__ x, int B,
+                                                   int H, int W)
+{
+    const long long HW = (long long)H * W;
+    const long long P = B * HW;
+    for (long long p = (long long)blockIdx.x * kT + threadIdx.x; p < P; p += (long long)gridDim.x * kT) {
+        const long long b = p / HW;
+        const long long q = p - b * HW;
+        bf16x8 v = zero8();
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            v[c] = (__bf16)f[(b * 3 + c) * HW + q];
+        *(bf16x8 *)(x + (size_t)p * 8) = v;
+    }
+}
+
+// 2x2 max pooling of [B][H][W][C] (C % 8 == 0).
+__global__ __launch_bounds__(kT) void k_maxpool(const __bf16 *__restrict__ x, __bf16 *__restrict__ y, int B, int H,
+                                                int W, int C)
+{
+    const int h = H / 2, w = W / 2, cg = C / 8;
+    const long long n = (long long)B * h * w * cg;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const int c8 = (int)(q % cg);
+        const long long o = q / cg;
+        const int j = (int)(o % w);
+        const int i = (int)((o / w) % h);
+        const long long b = o / ((long long)w * h);
+        const __bf16 *base = x + ((size_t)(b * H + 2 * i) * W + 2 * j) * C + c8 * 8;
+        bf16x8 m = *(const bf16x8 *)base;
+        const bf16x8 v1 = *(const bf16x8 *)(base + C);
+        const bf16x8 v2 = *(const bf16x8 *)(base + (size_t)W * C);
+        const bf16x8 v3 = *(const bf16x8 *)(base + (size_t)W * C + C);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float a = (float)m[t];
+            a = (float)v1[t] > a ? (float)v1[t] : a;
+            a = (float)v2[t] > a ? (float)v2[t] : a;
+            a = (float)v3[t] > a ? (float)v3[t] : a;
+            m[t] = (__bf16)a;
+        }
+        *(bf16x8 *)(y + (size_t)o * C + c8 * 8) = m;
+    }
+}
+
+// dx += dy routed to each window's first maximum (row-major window order),
+// then dx *= (x > 0) over the window (the ReLU of the layer producing x).
+__global__ __launch_bounds__(kT) void k_maxpool_bwd(const __bf16 *__restrict__ x, const __bf16 *__restrict__ dy,
+                                                    __bf16 *__restrict__ dx, int B, int H, int W, int C)
+{
+    const int h = H / 2, w = W / 2;
+    const long long n = (long long)B * h * w * C;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const int c = (int)(q % C);
+        const long long o = q / C;
+        const int j = (int)(o % w);
+        const int i = (int)((o / w) % h);
+        const long long b = o / ((long long)w * h);
+        size_t idx[4];
+        idx[0] = ((size_t)(b * H + 2 * i) * W + 2 * j) * C + c;
+        idx[1] = idx[0] + C;
+        idx[2] = idx[0] + (size_t)W * C;
+        idx[3] = idx[2] + C;
+        int am = 0;
+        float mv = (float)x[idx[0]];
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+            const float v = (float)x[idx[t]];
+            if (v > mv) {
+                mv = v;
+                am = t;
+            }
+        }
+        const float g = (float)dy[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float v = (float)dx[idx[t]] + (t == am ? g : 0.f);
+            if (!((float)x[idx[t]] > 0.f))
+                v = 0.f;
+            dx[idx[t]] = (__bf16)v;
+        }
+    }
+}
+
+// out [B][2h][2w][C1 + C2] = [nearest-upsampled low [B][h][w][C1], skip].
+__global__ __launch_bounds__(kT) void k_up_concat(const __bf16 *__restrict__ low, const __bf16 *__restrict__ skip,
+                                                  __bf16 *__restrict__ out, int B, int H, int W, int C1, int C2)
+{
+    const int C = C1 + C2, cg = C / 8;
+    const long long n = (long long)B * H * W * cg;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const int c8 = (int)(q % cg) * 8;
+        const long long p = q / cg;
+        const int x = (int)(p % W);
+        const int y = (int)((p / W) % H);
+        const long long b = p / ((long long)W * H);
+        bf16x8 v;
+        if (c8 < C1)
+            v = *(const bf16x8 *)(low + ((size_t)(b * (H / 2) + y / 2) * (W / 2) + x / 2) * C1 + c8);
+        else
+            v = *(const bf16x8 *)(skip + (size_t)p * C2 + (c8 - C1));
+        *(bf16x8 *)(out + (size_t)p * C + c8) = v;
+    }
+}
+
+// Gradient of k_up_concat: dlow = (sum of the 4 children's first C1
+// channels) * (low > 0), dskip = (last C2 channels) * (skip > 0).
+__global__ __launch_bounds__(kT) void k_up_concat_bwd(const __bf16 *__restrict__ dcat, const __bf16 *__restrict__ low,
+                                                      const __bf16 *__restrict__ skip, __bf16 *__restrict__ dlow,
+                                                      __bf16 *__restrict__ dskip, int B, int H, int W, int C1, int C2)
+{
+    const int C = C1 + C2;
+    const int h = H / 2, w = W / 2;
+    const long long nl = (long long)B * h * w * C1;
+    const long long ns = (long long)B * H * W * C2;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < nl + ns; q += (long long)gridDim.x * kT) {
+        if (q < nl) {
+            const int c = (int)(q % C1);
+            const long long o = q / C1;
+            const int j = (int)(o % w);
+            const int i = (int)((o / w) % h);
+            const long long b = o / ((long long)w * h);
+            const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * C + c;
+            float a = (float)dcat[base] + (float)dcat[base + C];
+            a += (float)dcat[base + (size_t)W * C] + (float)dcat[base + (size_t)W * C + C];
+            dlow[q] = (__bf16)((float)low[q] > 0.f ? a : 0.f);
+        } else {
+            const long long r = q - nl;
+            const int c = (int)(r % C2);
+            const long long p = r / C2;
+            const float v = (float)dcat[(size_t)p * C + C1 + c];
+            dskip[r] = (__bf16)((float)skip[r] > 0.f ? v : 0.f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// loss
+
+constexpr int kOutC = TVSPEC_NET_OUT_CHANNELS;  // 15
+constexpr int kOutPad = 16;                       // channels of the last layer's output
+constexpr int kGroups = TVSPEC_NET_BANDS + 1;     // 4 bands + residual, 3 channels each
+
+// t [P][16] float from bands [B][4][3][H][W] and residual [B][3][H][W] (float64).
+__global__ __launch_bounds__(kT) void k_pack_target(const double *__restrict__ bands, const double *__restrict__ res,
+                                                    float *__restrict__ t, int B, long long HW)
+{
+    const long long P = B * HW;
+    for (long long p = (long long)blockIdx.x * kT + threadIdx.x; p < P; p += (long long)gridDim.x * kT) {
+        const long long b = p / HW;
+        const long long q = p - b * HW;
+        float *tp = t + (size_t)p * kOutPad;
+        for (int j = 0; j < TVSPEC_NET_BANDS; ++j)
+            for (int c = 0; c < 3; ++c)
+                tp[3 * j + c] = (float)bands[((b * TVSPEC_NET_BANDS + j) * 3 + c) * HW + q];
+        for (int c = 0; c < 3; ++c)
+            tp[12 + c] = (float)res[(b * 3 + c) * HW + q];
+        tp[15] = 0.f;
+    }
+}
+
+// o [P][16] float -> out [B][15][H][W].
+__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, float *__restrict__ out, int B,
+                                                      long long HW)
+{
+    const long long n = B * HW * kOutC;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const long long pix = q % HW;
+        const int c = (int)((q / HW) % kOutC);
+        const long long b = q / (HW * kOutC);
+        out[q] = o[(size_t)(b * HW + pix) * kOutPad + c];
+    }
+}
+
+__device__ __forceinline__ float block_sum(float v, float *sh)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// part[b][j][blk][2] = block sums of (o - t)^2 and t^2 over band j of image b.
+__global__ __launch_bounds__(kT) void k_loss_partial(const float *__restrict__ o, const float *__restrict__ t,
+                                                     long long HW, float *__restrict__ part)
+{
+    __shared__ float sh[4];
+    const int b = blockIdx.y;
+    const int nblk = gridDim.x;
+    float num[kGroups], den[kGroups];
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j)
+        num[j] = den[j] = 0.f;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < HW; q += (long long)nblk * kT) {
+        const float *op = o + (size_t)(b * HW + q) * kOutPad;
+        const float *tp = t + (size_t)(b * HW + q) * kOutPad;
+#pragma unroll
+        for (int j = 0; j < kGroups; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float e = op[3 * j + c] - tp[3 * j + c];
+                num[j] += e * e;
+                den[j] += tp[3 * j + c] * tp[3 * j + c];
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const float a = block_sum(num[j], sh);
+        const float d = block_sum(den[j], sh);
+        if (threadIdx.x == 0) {
+            part[((size_t)(b * kGroups + j) * nblk + blockIdx.x) * 2] = a;
+            part[((size_t)(b * kGroups + j) * nblk + blockIdx.x) * 2 + 1] = d;
+        }
+    }
+}
+
+// nd[b][j][2] = totals (fixed order); loss[0] = (1/(5B)) sum num/den.
+__global__ __launch_bounds__(64) void k_loss_total(const float *__restrict__ part, int B, int nblk,
+                                                   float *__restrict__ nd, float *__restrict__ loss)
+{
+    if (threadIdx.x != 0)
+        return;
+    double l = 0.0;
+    for (int bj = 0; bj < B * kGroups; ++bj) {
+        double a = 0.0, d = 0.0;
+        for (int k = 0; k < nblk; ++k) {
+            a += part[((size_t)bj * nblk + k) * 2];
+            d += part[((size_t)bj * nblk + k) * 2 + 1];
+        }
+        nd[2 * bj] = (float)a;
+        nd[2 * bj + 1] = (float)d;
+        l += d > 0.0 ? a / d : 0.0;
+    }
+    loss[0] = (float)(l / (double)(B * kGroups));
+}
+
+// do = 2 (o - t) / (den_bj 5 B) as bf16 [P][16] (channel 15 zero).
+__global__ __launch_bounds__(kT) void k_loss_grad(const float *__restrict__ o, const float *__restrict__ t,
+                                                  const float *__restrict__ nd, int B, long long HW,
+                                                  __bf16 *__restrict__ dO)
+{
+    const long long n = B * HW * kOutPad;
+    const float scale = 2.f / (float)(B * kGroups);
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const int c = (int)(q % kOutPad);
+        const long long b = q / (HW * kOutPad);
+        float v = 0.f;
+        if (c < kOutC) {
+            const float den = nd[2 * (b * kGroups + c / 3) + 1];
+            v = den > 0.f ? scale * (o[q] - t[q]) / den : 0.f;
+        }
+        dO[q] = (__bf16)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// parameters
+
+// Adam on flat float32 arrays (Kingma and Ba, with bias correction).
+__global__ __launch_bounds__(kT) void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                                             float *__restrict__ v, long long n, float lr, float b1, float b2,
+                                             float eps, float c1, float c2)
+{
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const float gq = g[q];
+        const float mq = b1 * m[q] + (1.f - b1) * gq;
+        const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+        m[q] = mq;
+        v[q] = vq;
+        w[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+    }
+}
+
+// Layer weights from the flat master vector: wq [cout][9][cin] bf16 (zero
+// for padded channels), bias [cout] float.
+__global__ __launch_bounds__(kT) void k_requant(const float *__restrict__ master, __bf16 *__restrict__ wq,
+                                                float *__restrict__ bias, int cout, int cin, int cout_r, int cin_r)
+{
+    const size_t n = (size_t)cout * 9 * cin;
+    const float *wm = master;
+    const float *bm = master + (size_t)cout_r * 9 * cin_r;
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n + cout; q += (size_t)gridDim.x * kT) {
+        if (q < n) {
+            const int c = (int)(q % cin);
+            const int tap = (int)((q / cin) % 9);
+            const int o = (int)(q / ((size_t)9 * cin));
+            wq[q] = (__bf16)((o < cout_r && c < cin_r) ? wm[((size_t)o * 9 + tap) * cin_r + c] : 0.f);
+        } else {
+            const int o = (int)(q - n);
+            bias[o] = o < cout_r ? bm[o] : 0.f;
+        }
+    }
+}
+
+// Flat gradient of one layer from the padded weight gradient dw [cout][9][cin]
+// and bias gradient db [cout].
+__global__ __launch_bounds__(kT) void k_grad_to_flat(const float *__restrict__ dw, const float *__restrict__ db,
+                                                     float *__restrict__ flat, int cout, int cin, int cout_r, int cin_r)
+{
+    const size_t n = (size_t)cout_r * 9 * cin_r;
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n + cout_r; q += (size_t)gridDim.x * kT) {
+        if (q < n) {
+            const int c = (int)(q % cin_r);
+            const int tap = (int)((q / cin_r) % 9);
+            const int o = (int)(q / ((size_t)9 * cin_r));
+            flat[q] = dw[((size_t)o * 9 + tap) * cin + c];
+        } else {
+            flat[q] = db[q - n];
+        }
+    }
+}
+
+int grid_for(long long n)
+{
+    long long b = (n + kT - 1) / kT;
+    if (b < 1)
+        b = 1;
+    if (b > 65536)
+        b = 65536;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// workspace shared by the raw convolution entry points and the network
+
+struct Work {
+    size_t part_bytes = 0;
+    float *part = nullptr;
+    size_t wd_bytes = 0;
+    __bf16 *wd = nullptr;
+};
+
+int ensure(void **p, size_t *have, size_t bytes)
+{
+    if (*p && *have >= bytes)
+        return TVSPEC_OK;
+    if (*p)
+        HIP_TRY(hipDeviceSynchronize());
+    if (*p)
+        (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    HIP_TRY(hipMalloc(p, bytes));
+    *have = bytes;
+    return TVSPEC_OK;
+}
+
+int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
+             const __bf16 *mask, void *y, bool f32, hipStream_t st)
+{
+    const long long P = (long long)B * H * W;
+    const dim3 grid((unsigned)((P + 127) / 128), (unsigned)((Cout + 63) / 64));
+    if (f32)
+        hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(kT), 0, st, x, w, bias, mask, y, B, H, W, Cin, Cout, relu);
+    else
+        hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(kT), 0, st, x, w, bias, mask, y, B, H, W, Cin, Cout, relu);
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+int conv_dgrad(Work &wk, const __bf16 *dy, int B, int H, int W, int Cout, const __bf16 *w, int Cin,
+               const __bf16 *mask, __bf16 *dx, hipStream_t st)
+{
+    const size_t nw = (size_t)Cout * 9 * Cin;
+    TVSPEC_TRY(ensure((void **)&wk.wd, &wk.wd_bytes, nw * sizeof(__bf16)));
+    hipLaunchKernelGGL(k_flip_transpose, dim3(grid_for((long long)nw)), dim3(kT), 0, st, w, wk.wd, Cout, Cin);
+    return conv_fwd(dy, B, H, W, Cout, wk.wd, nullptr, Cin, 0, mask, dx, false, st);
+}
+
+int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, float *dw,
+               float *db, hipStream_t st)
+{
+    const long long P = (long long)B * H * W;
+    const int K = 9 * Cin;
+    const int tk = (K + 63) / 64, to = (Cout + 63) / 64;
+    const long long chunks = (P + kWChunk - 1) / kWChunk;
+    // enough ranges to give the device ~2048 workgroups
+    long long ns = 2048 / ((long long)tk * to);
+    ns = ns < 1 ? 1 : ns;
+    ns = ns > chunks ? chunks : ns;
+    const int cps = (int)((chunks + ns - 1) / ns);
+    ns = (chunks + cps - 1) / cps;
+    const size_t n = (size_t)Cout * K;
+    const long long bcps = (P + 255) / 256;
+    const size_t need = ((size_t)ns * n + (size_t)256 * Cout) * sizeof(float);
+    TVSPEC_TRY(ensure((void **)&wk.part, &wk.part_bytes, need));
+    hipLaunchKernelGGL(k_wgrad, dim3(tk, to, (unsigned)ns), dim3(kT), 0, st, x, dy, wk.part, B, H, W, Cin, Cout, cps);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for((long long)n)), dim3(kT), 0, st, wk.part, (int)ns, n, dw);
+    if (db) {
+        float *bp = wk.part + (size_t)ns * n;
+        hipLaunchKernelGGL(k_bias_partial, dim3((Cout + kT - 1) / kT, 256), dim3(kT), 0, st, dy, P, Cout, bcps, bp);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(Cout)), dim3(kT), 0, st, bp, 256, (size_t)Cout, db);
+    }
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+std::mutex g_raw_mu;
+Work g_raw_work;
+
+// ---------------------------------------------------------------------------
+// the network
+
+struct Layer {
+    const char *name;
+    int cin_r, cout_r;   // real channel counts (parameter shapes)
+    int cin, cout;       // as stored (input padded to 8, output to 16)
+    long long off;       // offset of the weights in the flat parameter vector
+    __bf16 *wq = nullptr;
+    float *bias = nullptr;
+    float *dw = nullptr; // padded weight gradient
+    float *db = nullptr;
+};
+
+struct Act {
+    __bf16 *a = nullptr;  // activation
+    __bf16 *g = nullptr;  // its gradient
+    int H = 0, W = 0, C = 0;
+};
+
+} // namespace
+} // namespace nn
+} // namespace tvspec
+
+struct tvspec_net {
+    int dev = 0;
+    int H = 0, W = 0, maxB = 0;
+    std::vector<tvspec::nn::Layer> L;
+    long long nparams = 0;
+    float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    long long step = 0;
+    // activations: x0, e1a, e1b, p1, e2a, e2b, p2, e3a, e3b, p3, e4a, e4b, c3, d3a, d3b, c2, d2a, d2b, c1, d1a, d1b
+    tvspec::nn::Act A[21];
+    float *out = nullptr;     // [P][16]
+    float *tgt = nullptr;     // [P][16]
+    __bf16 *dout = nullptr;   // [P][16]
+    float *lpart = nullptr, *nd = nullptr, *loss = nullptr;
+    int lblk = 0;
+    tvspec::nn::Work wk;
+    std::vector<void *> allocs;
+    std::mutex mu;
+};
+
+namespace tvspec {
+namespace nn {
+namespace {
+
+enum { X0, E1A, E1B, P1, E2A, E2B, P2, E3A, E3B, P3, E4A, E4B, C3, D3A, D3B, C2, D2A, D2B, C1, D1A, D1B };
+
+constexpr int kW0 = 48, kW1 = 96, kW2 = 192, kW3 = 384;
+
+int net_alloc(tvspec_net *n, void **p, size_t bytes)
+{
+    HIP_TRY(hipMalloc(p, bytes));
+    n->allocs.push_back(*p);
+    return TVSPEC_OK;
+}
+
+uint64_t splitmix(uint64_t &s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double normal(uint64_t &s)
+{
+    // Box-Muller on two uniforms in (0, 1]
+    const double u1 = ((splitmix(s) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    const double u2 = ((splitmix(s) >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+int requant_all(tvspec_net *n, hipStream_t st)
+{
+    for (Layer &l : n->L) {
+        const size_t cnt = (size_t)l.cout * 9 * l.cin + l.cout;
+        hipLaunchKernelGGL(k_requant, dim3(grid_for((long long)cnt)), dim3(kT), 0, st, n->master + l.off, l.wq,
+                           l.bias, l.cout, l.cin, l.cout_r, l.cin_r);
+    }
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+int forward(tvspec_net *n, const float *f, int B, hipStream_t st)
+{
+    Act *A = n->A;
+    const int H = n->H, W = n->W;
+    hipLaunchKernelGGL(k_pack_input, dim3(grid_for((long long)B * H * W)), dim3(kT), 0, st, f, A[X0].a, B, H, W);
+    auto conv = [&](int li, int in, int out) {
+        const Layer &l = n->L[li];
+        return conv_fwd(A[in].a, B, A[in].H, A[in].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false, st);
+    };
+    auto pool = [&](int in, int out) {
+        const long long cnt = (long long)B * A[out].H * A[out].W * (A[in].C / 8);
+        hipLaunchKernelGGL(k_maxpool, dim3(grid_for(cnt)), dim3(kT), 0, st, A[in].a, A[out].a, B, A[in].H, A[in].W,
+                           A[in].C);
+    };
+    auto upcat = [&](int low, int skip, int out) {
+        const long long cnt = (long long)B * A[out].H * A[out].W * (A[out].C / 8);
+        hipLaunchKernelGGL(k_up_concat, dim3(grid_for(cnt)), dim3(kT), 0, st, A[low].a, A[skip].a, A[out].a, B,
+                           A[out].H, A[out].W, A[low].C, A[skip].C);
+    };
+    TVSPEC_TRY(conv(0, X0, E1A));
+    TVSPEC_TRY(conv(1, E1A, E1B));
+    pool(E1B, P1);
+    TVSPEC_TRY(conv(2, P1, E2A));
+    TVSPEC_TRY(conv(3, E2A, E2B));
+    pool(E2B, P2);
+    TVSPEC_TRY(conv(4, P2, E3A));
+    TVSPEC_TRY(conv(5, E3A, E3B));
+    pool(E3B, P3);
+    TVSPEC_TRY(conv(6, P3, E4A));
+    TVSPEC_TRY(conv(7, E4A, E4B));
+    upcat(E4B, E3B, C3);
+    TVSPEC_TRY(conv(8, C3, D3A));
+    TVSPEC_TRY(conv(9, D3A, D3B));
+    upcat(D3B, E2B, C2);
+    TVSPEC_TRY(conv(10, C2, D2A));
+    TVSPEC_TRY(conv(11, D2A, D2B));
+    upcat(D2B, E1B, C1);
+    TVSPEC_TRY(conv(12, C1, D1A));
+    TVSPEC_TRY(conv(13, D1A, D1B));
+    const Layer &lo = n->L[14];
+    TVSPEC_TRY(conv_fwd(A[D1B].a, B, H, W, lo.cin, lo.wq, lo.bias, lo.cout, 0, nullptr, n->out, true, st));
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+// Loss of the last forward pass against bands/residual; leaves dL/dout in n->dout.
+int loss_and_grad(tvspec_net *n, const double *bands, const double *res, int B, hipStream_t st)
+{
+    const long long HW = (long long)n->H * n->W;
+    hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, n->tgt, B, HW);
+    hipLaunchKernelGGL(k_loss_partial, dim3(n->lblk, B), dim3(kT), 0, st, n->out, n->tgt, HW, n->lpart);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd, B, HW,
+                       n->dout);
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+int backward(tvspec_net *n, int B, hipStream_t st)
+{
+    Act *A = n->A;
+    Work &wk = n->wk;
+    // layer li: input activation `in`, gradient of its (masked) output dz;
+    // writes the layer's parameter gradients and, if din >= 0, the gradient
+    // of its input masked by mask_in (the input's own ReLU) or unmasked
+    auto layer = [&](int li, int in, const __bf16 *dz, int din, bool mask_in) -> int {
+        const Layer &l = n->L[li];
+        TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, l.dw, l.db, st));
+        if (din >= 0)
+            TVSPEC_TRY(conv_dgrad(wk, dz, B, A[in].H, A[in].W, l.cout, l.wq, l.cin, mask_in ? A[in].a : nullptr,
+                                  A[din].g, st));
+        return TVSPEC_OK;
+    };
+    auto upcat_bwd = [&](int cat, int low, int skip) {
+        const long long cnt = (long long)B * (A[low].H * A[low].W * (long long)A[low].C +
+                                              A[skip].H * A[skip].W * (long long)A[skip].C);
+        hipLaunchKernelGGL(k_up_concat_bwd, dim3(grid_for(cnt)), dim3(kT), 0, st, A[cat].g, A[low].a, A[skip].a,
+                           A[low].g, A[skip].g, B, A[cat].H, A[cat].W, A[low].C, A[skip].C);
+    };
+    auto pool_bwd = [&](int x, int p) {
+        const long long cnt = (long long)B * A[p].H * A[p].W * A[p].C;
+        hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(cnt)), dim3(kT), 0, st, A[x].a, A[p].g, A[x].g, B, A[x].H,
+                           A[x].W, A[x].C);
+    };
+    TVSPEC_TRY(layer(14, D1B, n->dout, D1B, true));
+    TVSPEC_TRY(layer(13, D1A, A[D1B].g, D1A, true));
+    TVSPEC_TRY(layer(12, C1, A[D1A].g, C1, false));
+    upcat_bwd(C1, D2B, E1B);
+    TVSPEC_TRY(layer(11, D2A, A[D2B].g, D2A, true));
+    TVSPEC_TRY(layer(10, C2, A[D2A].g, C2, false));
+    upcat_bwd(C2, D3B, E2B);
+    TVSPEC_TRY(layer(9, D3A, A[D3B].g, D3A, true));
+    TVSPEC_TRY(layer(8, C3, A[D3A].g, C3, false));
+    upcat_bwd(C3, E4B, E3B);
+    TVSPEC_TRY(layer(7, E4A, A[E4B].g, E4A, true));
+    TVSPEC_TRY(layer(6, P3, A[E4A].g, P3, false));
+    pool_bwd(E3B, P3);
+    TVSPEC_TRY(layer(5, E3A, A[E3B].g, E3A, true));
+    TVSPEC_TRY(layer(4, P2, A[E3A].g, P2, false));
+    pool_bwd(E2B, P2);
+    TVSPEC_TRY(layer(3, E2A, A[E2B].g, E2A, true));
+    TVSPEC_TRY(layer(2, P1, A[E2A].g, P1, false));
+    pool_bwd(E1B, P1);
+    TVSPEC_TRY(layer(1, E1A, A[E1B].g, E1A, true));
+    TVSPEC_TRY(layer(0, X0, A[E1A].g, -1, false));
+    for (Layer &l : n->L) {
+        const size_t cnt = (size_t)l.cout_r * 9 * l.cin_r + l.cout_r;
+        hipLaunchKernelGGL(k_grad_to_flat, dim3(grid_for((long long)cnt)), dim3(kT), 0, st, l.dw, l.db,
+                           n->grad + l.off, l.cout, l.cin, l.cout_r, l.cin_r);
+    }
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+int check_batch(tvspec_net *n, int B)
+{
+    if (B < 1 || B > n->maxB)
+        return fail(TVSPEC_EINVAL, "B must be in [1, max_batch]");
+    return TVSPEC_OK;
+}
+
+} // namespace
+} // namespace nn
+} // namespace tvspec
+
+using namespace tvspec;
+using namespace tvspec::nn;
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" int tvspec_nn_conv3x3(const void *x, int B, int H, int W, int Cin, const void *w, const float *bias,
+                                 int Cout, int relu, void *y, int y_f32, void *stream)
+{
+    g_last_error.clear();
+    if (!x || !w || !y)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (B < 1 || H < 1 || W < 1 || Cin < 8 || Cin % 8 || Cout < 16 || Cout % 16 || (relu != 0 && relu != 1) ||
+        (y_f32 != 0 && y_f32 != 1) || (long long)B * H * W > (1LL << 31))
+        return fail(TVSPEC_EINVAL, "need B, H, W >= 1, Cin a multiple of 8, Cout a multiple of 16");
+    return conv_fwd((const __bf16 *)x, B, H, W, Cin, (const __bf16 *)w, bias, Cout, relu, nullptr, y, y_f32 == 1,
+                    (hipStream_t)stream);
+}
+
+extern "C" int tvspec_nn_conv3x3_dgrad(const void *dy, int B, int H, int W, int Cout, const void *w, int Cin,
+                                       const void *mask, void *dx, void *stream)
+{
+    g_last_error.clear();
+    if (!dy || !w || !dx)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (B < 1 || H < 1 || W < 1 || Cout < 8 || Cout % 8 || Cin < 16 || Cin % 16 ||
+        (long long)B * H * W > (1LL << 31))
+        return fail(TVSPEC_EINVAL, "need B, H, W >= 1, Cout a multiple of 8, Cin a multiple of 16");
+    std::lock_guard<std::mutex> lock(g_raw_mu);
+    return conv_dgrad(g_raw_work, (const __bf16 *)dy, B, H, W, Cout, (const __bf16 *)w, Cin, (const __bf16 *)mask,
+                      (__bf16 *)dx, (hipStream_t)stream);
+}
+
+extern "C" int tvspec_nn_conv3x3_wgrad(const void *x, const void *dy, int B, int H, int W, int Cin, int Cout,
+                                       float *dw, float *db, void *stream)
+{
+    g_last_error.clear();
+    if (!x || !dy || !dw)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (B < 1 || H < 1 || W < 1 || Cin < 8 || Cin % 8 || Cout < 8 || Cout % 8 || (long long)B * H * W > (1LL << 31))
+        return fail(TVSPEC_EINVAL, "need B, H, W >= 1, Cin and Cout multiples of 8");
+    std::lock_guard<std::mutex> lock(g_raw_mu);
+    return conv_wgrad(g_raw_work, (const __bf16 *)x, (const __bf16 *)dy, B, H, W, Cin, Cout, dw, db,
+                      (hipStream_t)stream);
+}
+
+extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long seed, tvspec_net **out)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    *out = nullptr;
+    if (H < 8 || W < 8 || H % 8 || W % 8 || max_batch < 1 || (long long)max_batch * H * W > (1LL << 31))
+        return fail(TVSPEC_EINVAL, "need H, W multiples of 8 (>= 8) and max_batch >= 1");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto n = new tvspec_net();
+    n->dev = dev;
+    n->H = H;
+    n->W = W;
+    n->maxB = max_batch;
+    struct Spec {
+        const char *name;
+        int cin, cout;
+    } spec[15] = {{"e1a", 3, kW0},         {"e1b", kW0, kW0},       {"e2a", kW0, kW1},       {"e2b", kW1, kW1},
+                  {"e3a", kW1, kW2},       {"e3b", kW2, kW2},       {"e4a", kW2, kW3},       {"e4b", kW3, kW3},
+                  {"d3a", kW3 + kW2, kW2}, {"d3b", kW2, kW2},       {"d2a", kW2 + kW1, kW1}, {"d2b", kW1, kW1},
+                  {"d1a", kW1 + kW0, kW0}, {"d1b", kW0, kW0},       {"out", kW0, kOutC}};
+    long long off = 0;
+    auto cleanup = [&](int rc) {
+        for (void *p : n->allocs)
+            (void)hipFree(p);
+        delete n;
+        return rc;
+    };
+    for (int i = 0; i < 15; ++i) {
+        Layer l;
+        l.name = spec[i].name;
+        l.cin_r = spec[i].cin;
+        l.cout_r = spec[i].cout;
+        l.cin = (spec[i].cin + 7) / 8 * 8;
+        l.cout = (spec[i].cout + 15) / 16 * 16;
+        l.off = off;
+        off += (long long)l.cout_r * 9 * l.cin_r + l.cout_r;
+        int rc = net_alloc(n, (void **)&l.wq, (size_t)l.cout * 9 * l.cin * sizeof(__bf16));
+        if (rc == TVSPEC_OK)
+            rc = net_alloc(n, (void **)&l.bias, (size_t)l.cout * sizeof(float));
+        if (rc == TVSPEC_OK)
+            rc = net_alloc(n, (void **)&l.dw, (size_t)l.cout * 9 * l.cin * sizeof(float));
+        if (rc == TVSPEC_OK)
+            rc = net_alloc(n, (void **)&l.db, (size_t)l.cout * sizeof(float));
+        if (rc != TVSPEC_OK)
+            return cleanup(rc);
+        n->L.push_back(l);
+    }
+    n->nparams = off;
+    const size_t pb = (size_t)off * sizeof(float);
+    for (float **p : {&n->master, &n->grad, &n->m, &n->v}) {
+        const int rc = net_alloc(n, (void **)p, pb);
+        if (rc != TVSPEC_OK)
+            return cleanup(rc);
+    }
+    struct ASpec {
+        int lvl, C;
+    } as[21] = {{0, 8},         {0, kW0}, {0, kW0}, {1, kW0},       {1, kW1}, {1, kW1}, {2, kW1},
+                {2, kW2},       {2, kW2}, {3, kW2}, {3, kW3},       {3, kW3}, {2, kW3 + kW2}, {2, kW2},
+                {2, kW2},       {1, kW2 + kW1}, {1, kW1}, {1, kW1}, {0, kW1 + kW0}, {0, kW0}, {0, kW0}};
+    for (int i = 0; i < 21; ++i) {
+        Act &a = n->A[i];
+        a.H = H >> as[i].lvl;
+        a.W = W >> as[i].lvl;
+        a.C = as[i].C;
+        const size_t bytes = (size_t)max_batch * a.H * a.W * a.C * sizeof(__bf16);
+        int rc = net_alloc(n, (void **)&a.a, bytes);
+        if (rc == TVSPEC_OK)
+            rc = net_alloc(n, (void **)&a.g, bytes);
+        if (rc != TVSPEC_OK)
+            return cleanup(rc);
+    }
+    const size_t P = (size_t)max_batch * H * W;
+    n->lblk = (int)std::min<long long>(256, ((long long)H * W + kT - 1) / kT);
+    int rc = net_alloc(n, (void **)&n->out, P * kOutPad * sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->tgt, P * kOutPad * sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->dout, P * kOutPad * sizeof(__bf16));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->lpart, (size_t)max_batch * kGroups * n->lblk * 2 * sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->nd, (size_t)max_batch * kGroups * 2 * sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->loss, sizeof(float));
+    if (rc != TVSPEC_OK)
+        return cleanup(rc);
+    // He-normal weights, zero biases
+    std::vector<float> h((size_t)off, 0.f);
+    uint64_t s = seed;
+    for (const Layer &l : n->L) {
+        const double sd = std::sqrt(2.0 / (9.0 * l.cin_r));
+        for (long long q = 0; q < (long long)l.cout_r * 9 * l.cin_r; ++q)
+            h[(size_t)(l.off + q)] = (float)(sd * normal(s));
+    }
+    if (hipMemcpy(n->master, h.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, pb) != hipSuccess || hipMemset(n->v, 0, pb) != hipSuccess)
+        return cleanup(fail(TVSPEC_EDEVICE, "parameter upload failed"));
+    if ((rc = requant_all(n, nullptr)) != TVSPEC_OK)
+        return cleanup(rc);
+    if (hipDeviceSynchronize() != hipSuccess)
+        return cleanup(fail(TVSPEC_EDEVICE, "device synchronisation failed"));
+    *out = n;
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_num_params(tvspec_net *net, long long *n)
+{
+    g_last_error.clear();
+    if (!net || !n)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    *n = net->nparams;
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_get_params(tvspec_net *net, float *host, long long n)
+{
+    g_last_error.clear();
+    if (!net || !host)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (n != net->nparams)
+        return fail(TVSPEC_EINVAL, "n must equal tvspec_net_num_params");
+    std::lock_guard<std::mutex> lock(net->mu);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(host, net->master, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_set_params(tvspec_net *net, const float *host, long long n)
+{
+    g_last_error.clear();
+    if (!net || !host)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (n != net->nparams)
+        return fail(TVSPEC_EINVAL, "n must equal tvspec_net_num_params");
+    std::lock_guard<std::mutex> lock(net->mu);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(net->master, host, (size_t)n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(net->m, 0, (size_t)n * sizeof(float)));
+    HIP_TRY(hipMemset(net->v, 0, (size_t)n * sizeof(float)));
+    net->step = 0;
+    TVSPEC_TRY(requant_all(net, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_forward(tvspec_net *net, const float *f, int B, float *out, void *stream)
+{
+    g_last_error.clear();
+    if (!net || !f || !out)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    TVSPEC_TRY(check_batch(net, B));
+    std::lock_guard<std::mutex> lock(net->mu);
+    hipStream_t st = (hipStream_t)stream;
+    TVSPEC_TRY(forward(net, f, B, st));
+    const long long HW = (long long)net->H * net->W;
+    hipLaunchKernelGGL(k_unpack_output, dim3(grid_for(B * HW * kOutC)), dim3(kT), 0, st, net->out, out, B, HW);
+    HIP_TRY(hipGetLastError());
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_loss_grad(tvspec_net *net, const float *f, const double *bands, const double *residual,
+                                    int B, float *loss, float *grads, void *stream)
+{
+    g_last_error.clear();
+    if (!net || !f || !bands || !residual || !loss)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    TVSPEC_TRY(check_batch(net, B));
+    std::lock_guard<std::mutex> lock(net->mu);
+    hipStream_t st = (hipStream_t)stream;
+    TVSPEC_TRY(forward(net, f, B, st));
+    TVSPEC_TRY(loss_and_grad(net, bands, residual, B, st));
+    TVSPEC_TRY(backward(net, B, st));
+    HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    if (grads)
+        HIP_TRY(hipMemcpyAsync(grads, net->grad, (size_t)net->nparams * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const double *bands, const double *residual,
+                                     int B, float lr, float *loss, void *stream)
+{
+    g_last_error.clear();
+    if (!net || !f || !bands || !residual || !loss)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (!(lr > 0.f) || !std::isfinite(lr))
+        return fail(TVSPEC_EINVAL, "lr must be finite and > 0");
+    TVSPEC_TRY(check_batch(net, B));
+    std::lock_guard<std::mutex> lock(net->mu);
+    hipStream_t st = (hipStream_t)stream;
+    TVSPEC_TRY(forward(net, f, B, st));
+    TVSPEC_TRY(loss_and_grad(net, bands, residual, B, st));
+    TVSPEC_TRY(backward(net, B, st));
+    net->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(net->nparams)), dim3(kT), 0, st, net->master, net->grad, net->m, net->v,
+                       net->nparams, lr, b1, b2, 1e-8f, c1, c2);
+    TVSPEC_TRY(requant_all(net, st));
+    HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_destroy(tvspec_net *net)
+{
+    g_last_error.clear();
+    if (!net)
+        return TVSPEC_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(net->dev);
+    (void)hipDeviceSynchronize();
+    for (void *p : net->allocs)
+        (void)hipFree(p);
+    if (net->wk.part)
+        (void)hipFree(net->wk.part);
+    if (net->wk.wd)
+        (void)hipFree(net->wk.wd);
+    (void)hipSetDevice(cur);
+    delete net;
+    return TVSPEC_OK;
+}

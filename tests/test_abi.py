@@ -39,6 +39,39 @@ def test_binding_covers_header(tv):
         assert callable(getattr(tv, n))
 
 
+NN_HEADER = os.path.join(ROOT, "include", "tvspec_nn.h")
+
+
+def test_nn_header_symbols_exported_and_bound():
+    text = re.sub(r"/\*.*?\*/", "", open(NN_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(tvspec_(?:nn|net)_\w+)\s*\(", text)))
+    assert len(names) >= 10
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2006_10004_amd import nn
+    assert sorted(nn.EXPORTS) == names
+    for n in names:
+        assert callable(getattr(nn, n))
+
+
+def test_nn_entry_validation():
+    """Shape checks of the surrogate's entry points run before device work."""
+    lib = ctypes.CDLL(LIB)
+    vp, ci = ctypes.c_void_p, ctypes.c_int
+    lib.tvspec_nn_conv3x3.argtypes = [vp, ci, ci, ci, ci, vp, vp, ci, ci, vp, ci, vp]
+    fake = vp(0x1000)
+    assert lib.tvspec_nn_conv3x3(fake, 1, 4, 4, 6, fake, None, 16, 0, fake, 0, None) == -1   # Cin % 8
+    assert lib.tvspec_nn_conv3x3(fake, 1, 4, 4, 8, fake, None, 24, 0, fake, 0, None) == -1   # Cout % 16
+    assert lib.tvspec_nn_conv3x3(fake, 0, 4, 4, 8, fake, None, 16, 0, fake, 0, None) == -1
+    lib.tvspec_net_create.argtypes = [ci, ci, ci, ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    h = vp()
+    for H, W, B in [(20, 32, 1), (32, 12, 1), (32, 32, 0)]:
+        assert lib.tvspec_net_create(H, W, B, 0, ctypes.byref(h)) == -1
+    lib.tvspec_net_destroy.argtypes = [vp]
+    assert lib.tvspec_net_destroy(None) == 0
+
+
 def test_version(tv):
     assert "gfx950" in tv.tvspec_version()
 

@@ -1,0 +1,191 @@
+"""GPU parity of the surrogate network's kernels against the oracle
+(oracle/nn_oracle.py).
+
+Convolutions: inputs, weights and biases on the grid k/16, |k| <= 8, are
+exact in bfloat16, their products are multiples of 1/256 and every sum here
+stays below 2^24/256 in magnitude, so the float32 accumulation of the matrix
+cores is exact: forward (float32 output), weight and bias gradients are
+compared bit for bit with the float64 oracle, and the input gradient
+(bfloat16 output) with the oracle rounded to bfloat16 (round to nearest
+even, what the kernel's conversion does).
+
+The whole network stores activations and their gradients in bfloat16
+(unit roundoff 2^-9 per rounding, one rounding per layer output, 15
+layers): its output, loss and parameter gradients are compared with the
+float64 oracle with the same parameters within a relative L2 tolerance of
+3e-2 (output, loss) and 1e-1 (gradients, which pass through the rounded
+activations twice).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import nn_oracle as orc_nn  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def nn():
+    from paper_2006_10004_amd import nn
+    assert torch.cuda.is_available()
+    return nn
+
+
+def grid16(rng, shape):
+    return rng.integers(-8, 9, size=shape).astype(np.float64) / 16.0
+
+
+def bf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).to(DEV)
+
+
+def to_bf16_np(a):
+    """float64 -> nearest bfloat16 (ties to even), back as float64."""
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout,relu", [(2, 13, 19, 8, 16, False), (1, 9, 33, 48, 48, True),
+                                                 (2, 16, 16, 144, 96, True), (1, 7, 5, 24, 64, False)])
+def test_conv3x3_forward_exact(nn, B, H, W, Cin, Cout, relu):
+    rng = np.random.default_rng(Cin * 7 + Cout)
+    x = grid16(rng, (B, H, W, Cin))
+    w = grid16(rng, (Cout, 3, 3, Cin))
+    b = grid16(rng, (Cout,))
+    ref = orc_nn.conv3x3(x, w, b)
+    if relu:
+        ref = orc_nn.relu(ref)
+    y = nn.tvspec_nn_conv3x3(bf(x), bf(w), torch.from_numpy(b.astype(np.float32)).to(DEV), relu=relu,
+                             out_f32=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().astype(np.float64), ref)
+    yb = nn.tvspec_nn_conv3x3(bf(x), bf(w), torch.from_numpy(b.astype(np.float32)).to(DEV), relu=relu)
+    torch.cuda.synchronize()
+    assert np.array_equal(yb.float().cpu().numpy().astype(np.float64), to_bf16_np(ref))
+
+
+@pytest.mark.parametrize("B,H,W,Cout,Cin,masked", [(2, 13, 19, 16, 48, False), (1, 10, 12, 48, 144, True),
+                                                   (2, 8, 8, 96, 16, True)])
+def test_conv3x3_dgrad_exact(nn, B, H, W, Cout, Cin, masked):
+    rng = np.random.default_rng(Cout * 5 + Cin)
+    dy = grid16(rng, (B, H, W, Cout))
+    w = grid16(rng, (Cout, 3, 3, Cin))
+    ref = orc_nn.conv3x3_dgrad(dy, w)
+    mask = None
+    if masked:
+        m = np.maximum(grid16(rng, (B, H, W, Cin)), 0.0)
+        ref = ref * (m > 0)
+        mask = bf(m)
+    dx = nn.tvspec_nn_conv3x3_dgrad(bf(dy), bf(w), mask=mask)
+    torch.cuda.synchronize()
+    assert np.array_equal(dx.float().cpu().numpy().astype(np.float64), to_bf16_np(ref))
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(2, 13, 19, 8, 16), (1, 9, 33, 48, 48), (2, 16, 16, 144, 96),
+                                            (3, 24, 40, 16, 8)])
+def test_conv3x3_wgrad_exact(nn, B, H, W, Cin, Cout):
+    rng = np.random.default_rng(Cin * 3 + Cout)
+    x = grid16(rng, (B, H, W, Cin))
+    dy = grid16(rng, (B, H, W, Cout))
+    dw, db = nn.tvspec_nn_conv3x3_wgrad(bf(x), bf(dy))
+    torch.cuda.synchronize()
+    assert np.array_equal(dw.cpu().numpy().astype(np.float64), orc_nn.conv3x3_wgrad(x, dy))
+    assert np.array_equal(db.cpu().numpy().astype(np.float64), orc_nn.bias_grad(dy))
+
+
+def oracle_params(p, nn):
+    out = {}
+    for name, (w, b) in nn.split_params(p).items():
+        out[name] = (w.astype(np.float64), b.astype(np.float64))
+    return out
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def small_net(nn):
+    net = nn.Net(32, 32, 2, seed=3)
+    p = net.get_params()
+    rng = np.random.default_rng(5)
+    p = p + 0.02 * rng.standard_normal(p.size).astype(np.float32)  # non-zero biases too
+    net.set_params(p)
+    yield net, p
+    net.close()
+
+
+def inputs(seed, B=2, H=32, W=32):
+    rng = np.random.default_rng(seed)
+    f = rng.random((B, 3, H, W)).astype(np.float32)
+    bands = 0.1 * rng.standard_normal((B, 4, 3, H, W))
+    res = rng.random((B, 3, H, W))
+    return f, bands, res
+
+
+def test_params_round_trip(nn, small_net):
+    net, p = small_net
+    assert net.num_params == sum(co * 9 * ci + co for _, ci, co in nn.LAYERS)
+    assert np.array_equal(net.get_params(), p)
+
+
+def test_network_forward_against_oracle(nn, small_net):
+    net, p = small_net
+    f, _, _ = inputs(1)
+    out = net.forward(torch.from_numpy(f).to(DEV))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)                          # [B,15,H,W]
+    model = orc_nn.UNetOracle(3, 15, (48, 96, 192, 384))
+    # the network sees the input rounded to bfloat16
+    x = to_bf16_np(np.transpose(f, (0, 2, 3, 1)).astype(np.float64))
+    y, _ = model.forward(oracle_params(p, nn), x)
+    ref = np.transpose(y, (0, 3, 1, 2))
+    assert rel(o, ref) < 3e-2, rel(o, ref)
+
+
+def test_network_loss_and_gradients_against_oracle(nn, small_net):
+    net, p = small_net
+    f, bands, res = inputs(2)
+    loss, g = net.loss_grad(torch.from_numpy(f).to(DEV), torch.from_numpy(bands).to(DEV),
+                            torch.from_numpy(res).to(DEV))
+    model = orc_nn.UNetOracle(3, 15, (48, 96, 192, 384))
+    x = to_bf16_np(np.transpose(f, (0, 2, 3, 1)).astype(np.float64))
+    params = oracle_params(p, nn)
+    y, cache = model.forward(params, x)
+    t = np.concatenate([bands.reshape(2, 12, 32, 32), res], axis=1).transpose(0, 2, 3, 1)
+    ref_loss, dy = orc_nn.nmse_loss(y, t, 5)
+    assert abs(loss - ref_loss) / ref_loss < 3e-2, (loss, ref_loss)
+    ref_g = model.backward(params, cache, dy)
+    gs = nn.split_params(g)
+    for name, _, _ in nn.LAYERS:
+        assert rel(gs[name][0], ref_g[name][0]) < 1e-1, (name, rel(gs[name][0], ref_g[name][0]))
+        assert rel(gs[name][1], ref_g[name][1]) < 1e-1, (name, rel(gs[name][1], ref_g[name][1]))
+
+
+def test_training_reduces_the_loss(nn):
+    net = nn.Net(32, 32, 2, seed=9)
+    f, bands, res = inputs(3)
+    ft, bt, rt = (torch.from_numpy(a).to(DEV) for a in (f, bands, res))
+    first = net.train_step(ft, bt, rt, 1e-3)
+    for _ in range(60):
+        last = net.train_step(ft, bt, rt, 1e-3)
+    assert np.isfinite(last) and last < 0.5 * first, (first, last)
+    net.close()
+
+
+def test_adam_step_against_oracle(nn):
+    """One training step moves every parameter by Adam's first step,
+    lr * g / (|g| + eps) (float32 update of the float32 master weights)."""
+    net = nn.Net(16, 16, 1, seed=4)
+    f, bands, res = inputs(4, B=1, H=16, W=16)
+    ft, bt, rt = (torch.from_numpy(a).to(DEV) for a in (f, bands, res))
+    p0 = net.get_params()
+    _, g = net.loss_grad(ft, bt, rt)
+    net.train_step(ft, bt, rt, 1e-3)
+    p1 = net.get_params()
+    w, _, _ = orc_nn.adam_step(p0.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    assert np.abs(p1 - w).max() < 1e-6
+    net.close()
