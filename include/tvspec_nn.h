@@ -16,6 +16,8 @@
  *   decoder: nearest 2x upsampling, concatenation [upsampled, skip] along
  *   channels, two 3x3 conv + ReLU; a final 3x3 conv (no activation) to
  *   out_channels = 4 bands x 3 colour channels + 3 residual channels = 15.
+ *   The first layer sees the image as 2 f - 1 (centred; images lie in
+ *   [0, 1]); this fixed map is part of the network.
  *
  * Arithmetic: bfloat16 weights and activations, float32 accumulation in
  * the matrix cores (v_mfma_f32_16x16x32_bf16), float32 biases, outputs,
@@ -126,6 +128,18 @@ TVSPEC_API int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
 TVSPEC_API int tvspec_net_loss_grad(tvspec_net *net, const float *f, const double *bands,
                                     const double *residual, int B, float *loss, float *grads,
                                     void *stream);
+
+/*
+ * Reconstruction-identity error of decompositions in the network's output
+ * layout (Eq. (7): f = sum of bands + residual):
+ *   err[b] = mean over the 3 channels and H x W pixels of
+ *            |f - sum_j band_j - residual|
+ * f device float32 [B][3][H][W], out device float32 [B][15][H][W], err
+ * device float32 [B].  Serving uses it to decide when a surrogate result
+ * falls back to the model-driven path.
+ */
+TVSPEC_API int tvspec_net_identity_error(const float *f, const float *out, int B, int H, int W, float *err,
+                                         void *stream);
 
 TVSPEC_API int tvspec_net_destroy(tvspec_net *net);
 

@@ -129,16 +129,31 @@ def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def _same(x):
+    return x
+
+
 class UNetOracle:
     """The encoder-decoder: widths w0..w3 at 1, 1/2, 1/4, 1/8 resolution,
     two 3x3 conv + ReLU per level, 2x2 max-pooling down, nearest upsampling,
     skip connections by channel concatenation (upsampled first), and a final
     3x3 conv to the output channels without activation.
 
-    params: dict name -> (w [O,3,3,C], b [O]) with the layer names below."""
+    params: dict name -> (w [O,3,3,C], b [O]) with the layer names below.
 
-    def __init__(self, cin, cout, widths):
+    Optional storage hooks (default: none, pure float64) apply a rounding at
+    the points where an implementation stores tensors in a narrower type:
+    act_store on every ReLU layer output, out_store on the network output,
+    grad_store on every stored activation gradient (each layer's input
+    gradient, the upsampling gradient, the pooled-plus-skip gradient).
+    Pooling, upsampling and concatenation move stored values and round
+    nothing."""
+
+    def __init__(self, cin, cout, widths, act_store=None, out_store=None, grad_store=None):
         self.cin, self.cout, self.widths = cin, cout, list(widths)
+        self.act_store = act_store or _same
+        self.out_store = out_store or _same
+        self.grad_store = grad_store or _same
         w0, w1, w2, w3 = self.widths
         self.layers = [("e1a", cin, w0), ("e1b", w0, w0), ("e2a", w0, w1), ("e2b", w1, w1),
                        ("e3a", w1, w2), ("e3b", w2, w2), ("e4a", w2, w3), ("e4b", w3, w3),
@@ -151,10 +166,10 @@ class UNetOracle:
         skips = []
         for lvl, (la, lb) in enumerate((("e1a", "e1b"), ("e2a", "e2b"), ("e3a", "e3b"), ("e4a", "e4b"))):
             c[la + "_in"] = a
-            a = relu(conv3x3(a, *p[la]))
+            a = self.act_store(relu(conv3x3(a, *p[la])))
             c[la] = a
             c[lb + "_in"] = a
-            a = relu(conv3x3(a, *p[lb]))
+            a = self.act_store(relu(conv3x3(a, *p[lb])))
             c[lb] = a
             if lvl < 3:
                 skips.append(a)
@@ -163,13 +178,13 @@ class UNetOracle:
         for (la, lb), s in zip((("d3a", "d3b"), ("d2a", "d2b"), ("d1a", "d1b")), reversed(skips)):
             a = np.concatenate([upsample2(a), s], axis=3)
             c[la + "_in"] = a
-            a = relu(conv3x3(a, *p[la]))
+            a = self.act_store(relu(conv3x3(a, *p[la])))
             c[la] = a
             c[lb + "_in"] = a
-            a = relu(conv3x3(a, *p[lb]))
+            a = self.act_store(relu(conv3x3(a, *p[lb])))
             c[lb] = a
         c["out_in"] = a
-        y = conv3x3(a, *p["out"])
+        y = self.out_store(conv3x3(a, *p["out"]))
         return y, c
 
     def backward(self, p, c, dy):
@@ -180,7 +195,7 @@ class UNetOracle:
             if act:
                 da = da * (c[name] > 0)
             g[name] = (conv3x3_wgrad(c[name + "_in"], da), bias_grad(da))
-            return conv3x3_dgrad(da, p[name][0])
+            return self.grad_store(conv3x3_dgrad(da, p[name][0]))
 
         d = layer("out", dy, act=False)
         widths = self.widths
@@ -190,10 +205,10 @@ class UNetOracle:
             d = layer(la, d)
             nup = d.shape[3] - wskip
             skip_grads.append(d[..., nup:])
-            d = upsample2_grad(d[..., :nup])
+            d = self.grad_store(upsample2_grad(d[..., :nup]))
         for lvl, (la, lb) in reversed(list(enumerate((("e1a", "e1b"), ("e2a", "e2b"), ("e3a", "e3b"), ("e4a", "e4b"))))):
             if lvl < 3:
-                d = maxpool2_grad(c["pool%d_in" % lvl], d) + skip_grads[lvl]
+                d = self.grad_store(maxpool2_grad(c["pool%d_in" % lvl], d) + skip_grads[lvl])
             d = layer(lb, d)
             d = layer(la, d)
         return g

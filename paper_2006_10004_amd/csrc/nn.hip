@@ -315,7 +315,8 @@ __global__ __launch_bounds__(kT) void k_bias_partial(const __bf16 *__restrict__ 
 // ---------------------------------------------------------------------------
 // layout, pooling, upsampling
 
-// f [B][3][H][W] float -> x [B][H][W][8] bf16, channels 3..7 zero.
+// f [B][3][H][W] float -> x [B][H][W][8] bf16 holding 2 f - 1 (the input
+// centred on zero, f in [0, 1] -> [-1, 1]), channels 3..7 zero.
 __global__ __launch_bounds__(kT) void k_pack_input(const float *__restrict__ f, __bf16 *__restrict__ x, int B,
                                                    int H, int W)
 {
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kT) void k_pack_input(const float *__restrict__ f, 
         bf16x8 v = zero8();
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            v[c] = (__bf16)f[(b * 3 + c) * HW + q];
+            v[c] = (__bf16)(2.f * f[(b * 3 + c) * HW + q] - 1.f);
         *(bf16x8 *)(x + (size_t)p * 8) = v;
     }
 }
@@ -572,6 +573,31 @@ __global__ __launch_bounds__(kT) void k_loss_grad(const float *__restrict__ o, c
         }
         dO[q] = (__bf16)v;
     }
+}
+
+// err[b] = mean over channels c and pixels of |f - sum_j band_j - residual|
+// for out [B][15][H][W] (channel 3j + c band j, 12 + c residual) and f
+// [B][3][H][W]: the reconstruction identity of the decomposition, Eq. (7),
+// as the network's output satisfies it.  One block per image.
+__global__ __launch_bounds__(kT) void k_identity_error(const float *__restrict__ f, const float *__restrict__ out,
+                                                       long long HW, float *__restrict__ err)
+{
+    __shared__ float sh[4];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (long long q = threadIdx.x; q < 3 * HW; q += kT) {
+        const int c = (int)(q / HW);
+        const long long pix = q - c * HW;
+        const float *ob = out + (size_t)b * kOutC * HW;
+        float r = f[((size_t)b * 3 + c) * HW + pix];
+        for (int j = 0; j < TVSPEC_NET_BANDS; ++j)
+            r -= ob[(size_t)(3 * j + c) * HW + pix];
+        r -= ob[(size_t)(12 + c) * HW + pix];
+        acc += fabsf(r);
+    }
+    const float t = block_sum((float)acc, sh);
+    if (threadIdx.x == 0)
+        err[b] = t / (float)(3 * HW);
 }
 
 // ---------------------------------------------------------------------------
@@ -1179,6 +1205,19 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
     TVSPEC_TRY(requant_all(net, st));
     HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_identity_error(const float *f, const float *out, int B, int H, int W, float *err,
+                                         void *stream)
+{
+    g_last_error.clear();
+    if (!f || !out || !err)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (B < 1 || B > 65535 || H < 1 || W < 1)
+        return fail(TVSPEC_EINVAL, "need 1 <= B <= 65535 and H, W >= 1");
+    hipLaunchKernelGGL(k_identity_error, dim3(B), dim3(kT), 0, (hipStream_t)stream, f, out, (long long)H * W, err);
+    HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
 

@@ -25,6 +25,7 @@ EXPORTS = (
     "tvspec_net_forward",
     "tvspec_net_train_step",
     "tvspec_net_loss_grad",
+    "tvspec_net_identity_error",
     "tvspec_net_destroy",
 )
 
@@ -57,6 +58,8 @@ _lib.tvspec_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i, _f, ctypes.POINTE
 _lib.tvspec_net_train_step.restype = _i
 _lib.tvspec_net_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_f), _vp, _vp]
 _lib.tvspec_net_loss_grad.restype = _i
+_lib.tvspec_net_identity_error.argtypes = [_vp, _vp, _i, _i, _i, _vp, _vp]
+_lib.tvspec_net_identity_error.restype = _i
 _lib.tvspec_net_destroy.argtypes = [_vp]
 _lib.tvspec_net_destroy.restype = _i
 
@@ -154,6 +157,15 @@ def tvspec_net_loss_grad(h, f, bands, residual, grads=True, stream=None):
     _check(_lib.tvspec_net_loss_grad(h, f.data_ptr(), bands.data_ptr(), residual.data_ptr(), f.shape[0],
                                      ctypes.byref(loss), g.ctypes.data if grads else None, _stream(f, stream)))
     return loss.value, g
+
+
+def tvspec_net_identity_error(f, out, stream=None):
+    """Per-image mean |f - sum of bands - residual| of outputs [B,15,H,W]."""
+    B, _, H, W = f.shape
+    err = torch.empty((B,), dtype=torch.float32, device=f.device)
+    _check(_lib.tvspec_net_identity_error(f.data_ptr(), out.data_ptr(), B, H, W, err.data_ptr(),
+                                          _stream(f, stream)))
+    return err
 
 
 def tvspec_net_destroy(h):

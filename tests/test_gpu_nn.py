@@ -10,11 +10,15 @@ compared bit for bit with the float64 oracle, and the input gradient
 even, what the kernel's conversion does).
 
 The whole network stores activations and their gradients in bfloat16
-(unit roundoff 2^-9 per rounding, one rounding per layer output, 15
-layers): its output, loss and parameter gradients are compared with the
-float64 oracle with the same parameters within a relative L2 tolerance of
-3e-2 (output, loss) and 1e-1 (gradients, which pass through the rounded
-activations twice).
+and its output in float32.  The oracle runs with the same storage
+roundings (its act/out/grad hooks), so both sides take the same ReLU and
+max-pooling decisions; what remains is float32 accumulation against float64
+(relative ~1e-6 per sum), which moves a stored value across a bfloat16
+rounding boundary only rarely.  Output and loss are compared within 1e-2
+relative L2, every parameter gradient within 3e-2.  Without the hooks
+(pure float64 oracle) the first layer's gradient differs by ~15%: ties
+in bfloat16 max-pooling windows and ReLU inputs near zero route gradients
+differently.
 """
 import numpy as np
 import pytest
@@ -132,18 +136,27 @@ def test_params_round_trip(nn, small_net):
     assert np.array_equal(net.get_params(), p)
 
 
+def to_f32_np(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def stored_model():
+    return orc_nn.UNetOracle(3, 15, (48, 96, 192, 384), act_store=to_bf16_np, out_store=to_f32_np,
+                             grad_store=to_bf16_np)
+
+
 def test_network_forward_against_oracle(nn, small_net):
     net, p = small_net
     f, _, _ = inputs(1)
     out = net.forward(torch.from_numpy(f).to(DEV))
     torch.cuda.synchronize()
     o = out.cpu().numpy().astype(np.float64)                          # [B,15,H,W]
-    model = orc_nn.UNetOracle(3, 15, (48, 96, 192, 384))
-    # the network sees the input rounded to bfloat16
-    x = to_bf16_np(np.transpose(f, (0, 2, 3, 1)).astype(np.float64))
+    model = stored_model()
+    # the network sees 2 f - 1 rounded to bfloat16
+    x = to_bf16_np(2.0 * np.transpose(f, (0, 2, 3, 1)).astype(np.float64) - 1.0)
     y, _ = model.forward(oracle_params(p, nn), x)
     ref = np.transpose(y, (0, 3, 1, 2))
-    assert rel(o, ref) < 3e-2, rel(o, ref)
+    assert rel(o, ref) < 1e-2, rel(o, ref)
 
 
 def test_network_loss_and_gradients_against_oracle(nn, small_net):
@@ -151,18 +164,18 @@ def test_network_loss_and_gradients_against_oracle(nn, small_net):
     f, bands, res = inputs(2)
     loss, g = net.loss_grad(torch.from_numpy(f).to(DEV), torch.from_numpy(bands).to(DEV),
                             torch.from_numpy(res).to(DEV))
-    model = orc_nn.UNetOracle(3, 15, (48, 96, 192, 384))
-    x = to_bf16_np(np.transpose(f, (0, 2, 3, 1)).astype(np.float64))
+    model = stored_model()
+    x = to_bf16_np(2.0 * np.transpose(f, (0, 2, 3, 1)).astype(np.float64) - 1.0)
     params = oracle_params(p, nn)
     y, cache = model.forward(params, x)
-    t = np.concatenate([bands.reshape(2, 12, 32, 32), res], axis=1).transpose(0, 2, 3, 1)
+    t = to_f32_np(np.concatenate([bands.reshape(2, 12, 32, 32), res], axis=1).transpose(0, 2, 3, 1))
     ref_loss, dy = orc_nn.nmse_loss(y, t, 5)
-    assert abs(loss - ref_loss) / ref_loss < 3e-2, (loss, ref_loss)
-    ref_g = model.backward(params, cache, dy)
+    assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
+    ref_g = model.backward(params, cache, to_bf16_np(dy))
     gs = nn.split_params(g)
     for name, _, _ in nn.LAYERS:
-        assert rel(gs[name][0], ref_g[name][0]) < 1e-1, (name, rel(gs[name][0], ref_g[name][0]))
-        assert rel(gs[name][1], ref_g[name][1]) < 1e-1, (name, rel(gs[name][1], ref_g[name][1]))
+        assert rel(gs[name][0], ref_g[name][0]) < 3e-2, (name, rel(gs[name][0], ref_g[name][0]))
+        assert rel(gs[name][1], ref_g[name][1]) < 3e-2, (name, rel(gs[name][1], ref_g[name][1]))
 
 
 def test_training_reduces_the_loss(nn):
