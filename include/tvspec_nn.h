@@ -87,8 +87,10 @@ typedef struct tvspec_net tvspec_net;
 /*
  * Create the network for images of H x W (multiples of 8) and batches of up
  * to max_batch, on the current device, with He-normal weights drawn from a
- * counter-based generator seeded by `seed` and zero biases.  Activations,
- * gradients and Adam state for max_batch are allocated here.
+ * counter-based generator seeded by `seed`, zero biases and a zero output
+ * layer (so training starts from zero bands, loss 1 per band), and output
+ * scales of 1.  Activations, gradients and Adam state for max_batch are
+ * allocated here.
  */
 TVSPEC_API int tvspec_net_create(int H, int W, int max_batch, unsigned long long seed, tvspec_net **out);
 
@@ -101,6 +103,15 @@ TVSPEC_API int tvspec_net_create(int H, int W, int max_batch, unsigned long long
 TVSPEC_API int tvspec_net_num_params(tvspec_net *net, long long *n);
 TVSPEC_API int tvspec_net_get_params(tvspec_net *net, float *host, long long n);
 TVSPEC_API int tvspec_net_set_params(tvspec_net *net, const float *host, long long n);
+
+/*
+ * Fixed (not trained) scale of each output channel: output c =
+ * scale[c] * (the last convolution's channel c).  The bands of a
+ * decomposition are small next to the image (their RMS can be 1e-3 of it);
+ * scaling each output by its band's typical size lets the last layer work
+ * in units of order 1.  scale: host float32 [15], each > 0.
+ */
+TVSPEC_API int tvspec_net_set_output_scale(tvspec_net *net, const float *scale);
 
 /*
  * Forward pass.  f device float32 [B][3][H][W]; out device float32

@@ -187,14 +187,20 @@ class UNetOracle:
         y = self.out_store(conv3x3(a, *p["out"]))
         return y, c
 
-    def backward(self, p, c, dy):
-        """Gradients of <dy, forward(p, x)> in every parameter."""
+    def backward(self, p, c, dy, scales=None):
+        """Gradients of <dy, forward(p, x)> in every parameter.  If `scales`
+        is a dict it receives, per layer, the same sums taken over absolute
+        values, (wgrad(|x|, |da|), sum |da|): the size of the terms each
+        gradient entry adds up, against which its rounding error is judged
+        (the sums cancel, so their own size is no scale)."""
         g = {}
 
         def layer(name, da, act=True):
             if act:
                 da = da * (c[name] > 0)
             g[name] = (conv3x3_wgrad(c[name + "_in"], da), bias_grad(da))
+            if scales is not None:
+                scales[name] = (conv3x3_wgrad(np.abs(c[name + "_in"]), np.abs(da)), bias_grad(np.abs(da)))
             return self.grad_store(conv3x3_dgrad(da, p[name][0]))
 
         d = layer("out", dy, act=False)

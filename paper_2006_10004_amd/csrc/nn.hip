@@ -61,12 +61,13 @@ __device__ __forceinline__ bf16x8 zero8()
 
 // Y[p][o] = epilogue(sum_k A[p][k] Wt[o][k]), Wt [Cout][9][Cin].
 // Epilogue: + bias[o] (bias != nullptr), max(., 0) (relu), zero where
-// mask[p][o] <= 0 (mask != nullptr); stored as bf16 or f32.
+// mask[p][o] <= 0 (mask != nullptr), times oscale[o] (oscale != nullptr);
+// stored as bf16 or f32.
 template <bool F32OUT>
 __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
                                                 const float *__restrict__ bias, const __bf16 *__restrict__ mask,
-                                                void *__restrict__ Y, int B, int H, int W, int Cin, int Cout,
-                                                int relu)
+                                                const float *__restrict__ oscale, void *__restrict__ Y, int B,
+                                                int H, int W, int Cin, int Cout, int relu)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, co
             if (co >= Cout)
                 continue;
             const float bv = bias ? bias[co] : 0.f;
+            const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long long p = p0 + r * 16 + 4 * g + i;
@@ -165,6 +167,8 @@ __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, co
                     v = v > 0.f ? v : 0.f;
                 if (mask && !((float)mask[(size_t)p * Cout + co] > 0.f))
                     v = 0.f;
+                if (oscale)
+                    v *= sv;
                 if constexpr (F32OUT)
                     ((float *)Y)[(size_t)p * Cout + co] = v;
                 else
@@ -556,10 +560,11 @@ __global__ __launch_bounds__(64) void k_loss_total(const float *__restrict__ par
     loss[0] = (float)(l / (double)(B * kGroups));
 }
 
-// do = 2 (o - t) / (den_bj 5 B) as bf16 [P][16] (channel 15 zero).
+// do = 2 (o - t) / (den_bj 5 B) times the output scale of the channel (the
+// gradient before the scale), as bf16 [P][16] (channel 15 zero).
 __global__ __launch_bounds__(kT) void k_loss_grad(const float *__restrict__ o, const float *__restrict__ t,
-                                                  const float *__restrict__ nd, int B, long long HW,
-                                                  __bf16 *__restrict__ dO)
+                                                  const float *__restrict__ nd, const float *__restrict__ oscale,
+                                                  int B, long long HW, __bf16 *__restrict__ dO)
 {
     const long long n = B * HW * kOutPad;
     const float scale = 2.f / (float)(B * kGroups);
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(kT) void k_loss_grad(const float *__restrict__ o, c
         float v = 0.f;
         if (c < kOutC) {
             const float den = nd[2 * (b * kGroups + c / 3) + 1];
-            v = den > 0.f ? scale * (o[q] - t[q]) / den : 0.f;
+            v = den > 0.f ? scale * (o[q] - t[q]) / den * oscale[c] : 0.f;
         }
         dO[q] = (__bf16)v;
     }
@@ -693,14 +698,16 @@ int ensure(void **p, size_t *have, size_t bytes)
 }
 
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
-             const __bf16 *mask, void *y, bool f32, hipStream_t st)
+             const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr)
 {
     const long long P = (long long)B * H * W;
     const dim3 grid((unsigned)((P + 127) / 128), (unsigned)((Cout + 63) / 64));
     if (f32)
-        hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(kT), 0, st, x, w, bias, mask, y, B, H, W, Cin, Cout, relu);
+        hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin, Cout,
+                           relu);
     else
-        hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(kT), 0, st, x, w, bias, mask, y, B, H, W, Cin, Cout, relu);
+        hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin, Cout,
+                           relu);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -782,6 +789,7 @@ struct tvspec_net {
     float *tgt = nullptr;     // [P][16]
     __bf16 *dout = nullptr;   // [P][16]
     float *lpart = nullptr, *nd = nullptr, *loss = nullptr;
+    float *oscale = nullptr;  // [16] output channel scales (1 by default)
     int lblk = 0;
     tvspec::nn::Work wk;
     std::vector<void *> allocs;
@@ -870,7 +878,8 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st)
     TVSPEC_TRY(conv(12, C1, D1A));
     TVSPEC_TRY(conv(13, D1A, D1B));
     const Layer &lo = n->L[14];
-    TVSPEC_TRY(conv_fwd(A[D1B].a, B, H, W, lo.cin, lo.wq, lo.bias, lo.cout, 0, nullptr, n->out, true, st));
+    TVSPEC_TRY(conv_fwd(A[D1B].a, B, H, W, lo.cin, lo.wq, lo.bias, lo.cout, 0, nullptr, n->out, true, st,
+                        n->oscale));
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -882,8 +891,8 @@ int loss_and_grad(tvspec_net *n, const double *bands, const double *res, int B, 
     hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, n->tgt, B, HW);
     hipLaunchKernelGGL(k_loss_partial, dim3(n->lblk, B), dim3(kT), 0, st, n->out, n->tgt, HW, n->lpart);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
-    hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd, B, HW,
-                       n->dout);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd,
+                       n->oscale, B, HW, n->dout);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1087,12 +1096,22 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
         rc = net_alloc(n, (void **)&n->nd, (size_t)max_batch * kGroups * 2 * sizeof(float));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->loss, sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->oscale, kOutPad * sizeof(float));
     if (rc != TVSPEC_OK)
         return cleanup(rc);
-    // He-normal weights, zero biases
+    {
+        const float ones[kOutPad] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 0.f};
+        if (hipMemcpy(n->oscale, ones, sizeof(ones), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(TVSPEC_EDEVICE, "output scale upload failed"));
+    }
+    // He-normal weights, zero biases; the output layer starts at zero, so the
+    // first outputs are 0 and every band's loss term starts at 1
     std::vector<float> h((size_t)off, 0.f);
     uint64_t s = seed;
     for (const Layer &l : n->L) {
+        if (&l == &n->L.back())
+            continue;
         const double sd = std::sqrt(2.0 / (9.0 * l.cin_r));
         for (long long q = 0; q < (long long)l.cout_r * 9 * l.cin_r; ++q)
             h[(size_t)(l.off + q)] = (float)(sd * normal(s));
@@ -1145,6 +1164,24 @@ extern "C" int tvspec_net_set_params(tvspec_net *net, const float *host, long lo
     net->step = 0;
     TVSPEC_TRY(requant_all(net, nullptr));
     HIP_TRY(hipDeviceSynchronize());
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_set_output_scale(tvspec_net *net, const float *scale)
+{
+    g_last_error.clear();
+    if (!net || !scale)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    float h[kOutPad];
+    for (int c = 0; c < kOutC; ++c) {
+        if (!(scale[c] > 0.f) || !std::isfinite(scale[c]))
+            return fail(TVSPEC_EINVAL, "output scales must be finite and > 0");
+        h[c] = scale[c];
+    }
+    h[kOutC] = 0.f;
+    std::lock_guard<std::mutex> lock(net->mu);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(net->oscale, h, sizeof(h), hipMemcpyHostToDevice));
     return TVSPEC_OK;
 }
 

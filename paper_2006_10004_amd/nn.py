@@ -22,6 +22,7 @@ EXPORTS = (
     "tvspec_net_num_params",
     "tvspec_net_get_params",
     "tvspec_net_set_params",
+    "tvspec_net_set_output_scale",
     "tvspec_net_forward",
     "tvspec_net_train_step",
     "tvspec_net_loss_grad",
@@ -52,6 +53,8 @@ _lib.tvspec_net_get_params.argtypes = [_vp, _vp, _ll]
 _lib.tvspec_net_get_params.restype = _i
 _lib.tvspec_net_set_params.argtypes = [_vp, _vp, _ll]
 _lib.tvspec_net_set_params.restype = _i
+_lib.tvspec_net_set_output_scale.argtypes = [_vp, _vp]
+_lib.tvspec_net_set_output_scale.restype = _i
 _lib.tvspec_net_forward.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.tvspec_net_forward.restype = _i
 _lib.tvspec_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i, _f, ctypes.POINTER(_f), _vp]
@@ -140,6 +143,13 @@ def tvspec_net_set_params(h, p):
     _check(_lib.tvspec_net_set_params(h, p.ctypes.data, p.size))
 
 
+def tvspec_net_set_output_scale(h, scale):
+    s = np.ascontiguousarray(scale, dtype=np.float32)
+    if s.shape != (OUT_CHANNELS,):
+        raise ValueError("scale must have %d entries" % OUT_CHANNELS)
+    _check(_lib.tvspec_net_set_output_scale(h, s.ctypes.data))
+
+
 def tvspec_net_forward(h, f, out, stream=None):
     _check(_lib.tvspec_net_forward(h, f.data_ptr(), f.shape[0], out.data_ptr(), _stream(f, stream)))
 
@@ -188,6 +198,7 @@ class Net:
     def __init__(self, H, W, max_batch, seed=0):
         self.H, self.W, self.max_batch = H, W, max_batch
         self._h = tvspec_net_create(H, W, max_batch, seed)
+        self.output_scale = np.ones(OUT_CHANNELS, dtype=np.float32)
 
     def _check_f(self, f):
         if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32 or f.dim() != 4 \
@@ -211,6 +222,11 @@ class Net:
 
     def set_params(self, p):
         tvspec_net_set_params(self._h, p)
+
+    def set_output_scale(self, scale):
+        """Fixed per-channel output scales [15] (see the header)."""
+        tvspec_net_set_output_scale(self._h, scale)
+        self.output_scale = np.asarray(scale, dtype=np.float32)
 
     def forward(self, f, out=None, stream=None):
         """f [B,3,H,W] float32 -> [B,15,H,W] float32 (4 bands x 3, residual x 3)."""

@@ -1,0 +1,171 @@
+"""The learned surrogate's pipeline around the library: training data from
+the model-driven path, training, evaluation and serving with fallback.
+
+Sec. 3 of the paper trains a network on decompositions the model-driven
+method computes (its ground truth) and Sec. 4.3 compares their cost.  Here:
+
+  make_images        seeded synthetic 3-channel shape images (synth.py)
+  decompose_dataset  their decompositions by the batched GPU path
+                     (tvspec_decompose_batch_dev) with the flow FLOW
+  train              Adam steps of tvspec_net_train_step on random minibatches
+  band_errors        relative L1 error of predicted bands and residual
+  SurrogateService   network inference with the reconstruction-identity check:
+                     a result whose identity error exceeds the threshold is
+                     replaced by the model-driven decomposition, and every
+                     `judge_every`-th image is also decomposed by the
+                     model-driven path to measure the surrogate's band error.
+
+All arithmetic of the decomposition and of the network runs in the HIP
+library; torch only holds device memory, gathers minibatches and computes
+the evaluation metrics.
+"""
+from __future__ import annotations
+
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import torch
+
+from . import synth, tvspec
+from .nn import BANDS, IN_CHANNELS, OUT_CHANNELS, Net, tvspec_net_identity_error
+
+# The decomposition the network learns: dt 0.005, K 100 samples, 150 inner
+# iterations per ROF solve, 4 dyadic bands {0, 1, 2, 4, 100} and the residual.
+FLOW = dict(dt=0.005, K=100, iters=150, edges=[0, 1, 2, 4, 100])
+
+
+def make_images(n, side, seed0, threads=16):
+    """n seeded images [n, 3, side, side] float32 (synth.serving_spec)."""
+    spec = synth.serving_spec(side)
+    out = np.empty((n, IN_CHANNELS, side, side), np.float32)
+
+    def work(i):
+        out[i] = synth.shapes_image(spec, seed0 + i)
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, range(n)))
+    return out
+
+
+def decompose_dataset(f, flow=FLOW, chunk=64, precision="mixed"):
+    """Bands [n, 4, 3, H, W] and residual [n, 3, H, W] (float64, on f's device)
+    of the images f [n, 3, H, W] by the batched model-driven path."""
+    n, C, H, W = f.shape
+    bands = torch.empty((n, BANDS, C, H, W), dtype=torch.float64, device=f.device)
+    res = torch.empty((n, C, H, W), dtype=torch.float64, device=f.device)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        outs = tvspec.tvspec_decompose_batch_dev(f[a:b].contiguous(), [flow["dt"]] * (b - a),
+                                                 [flow["K"]] * (b - a), flow["iters"], [flow["edges"]] * (b - a),
+                                                 precision=precision)
+        for i, o in enumerate(outs):
+            bands[a + i].copy_(o["bands"])
+            res[a + i].copy_(o["residual"])
+    return bands, res
+
+
+def output_scales(bands, res):
+    """Output scales [15]: the RMS of each band over a dataset (its three
+    colour channels share it) and of the residual."""
+    s = np.empty(OUT_CHANNELS, np.float32)
+    for j in range(BANDS):
+        s[3 * j:3 * j + 3] = float(bands[:, j].pow(2).mean().sqrt())
+    s[3 * BANDS:] = float(res.pow(2).mean().sqrt())
+    return s
+
+
+def train(net, f, bands, res, steps, batch, lr, seed=0):
+    """`steps` Adam steps on minibatches drawn uniformly from the dataset."""
+    g = torch.Generator().manual_seed(seed)
+    n = f.shape[0]
+    losses = []
+    for _ in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(f.device)
+        losses.append(net.train_step(f.index_select(0, idx).contiguous(), bands.index_select(0, idx).contiguous(),
+                                     res.index_select(0, idx).contiguous(), lr))
+    return losses
+
+
+def split_output(out):
+    """[B, 15, H, W] -> (bands [B, 4, 3, H, W], residual [B, 3, H, W])."""
+    B, _, H, W = out.shape
+    return out[:, :3 * BANDS].reshape(B, BANDS, IN_CHANNELS, H, W), out[:, 3 * BANDS:]
+
+
+def band_errors(out, bands, res):
+    """Relative L1 error sum|pred - ref| / sum|ref| per band and for the
+    residual, over a batch; and the same over all bands together."""
+    pb, pr = split_output(out)
+    e = {}
+    for j in range(BANDS):
+        e["band%d" % (j + 1)] = float((pb[:, j].double() - bands[:, j]).abs().sum() / bands[:, j].abs().sum())
+    e["residual"] = float((pr.double() - res).abs().sum() / res.abs().sum())
+    e["all_bands"] = float((pb.double() - bands).abs().sum() / bands.abs().sum())
+    return e
+
+
+def conv_flops(H, W):
+    """Multiply-add flops (2 per MAC) of one forward pass on an H x W image."""
+    from .nn import LAYERS
+    lvl = {"e1": 0, "e2": 1, "e3": 2, "e4": 3, "d3": 2, "d2": 1, "d1": 0, "ou": 0}
+    total = 0
+    for name, ci, co in LAYERS:
+        s = 2 ** lvl[name[:2]]
+        total += 2 * 9 * ci * co * (H // s) * (W // s)
+    return total
+
+
+class SurrogateService:
+    """Decompositions by the network, with the model-driven path as fallback
+    (identity error above `threshold`) and as judge (every `judge_every`-th
+    image, 0 = never)."""
+
+    def __init__(self, net: Net, threshold=1e-2, judge_every=16, flow=FLOW, precision="mixed"):
+        self.net, self.threshold, self.judge_every = net, threshold, judge_every
+        self.flow, self.precision = flow, precision
+        self.count = 0
+        self.judged = []      # band-error dicts of judged images
+        self.fallbacks = 0
+
+    def _plain(self, f):
+        n = f.shape[0]
+        fl = self.flow
+        return tvspec.tvspec_decompose_batch_dev(f.contiguous(), [fl["dt"]] * n, [fl["K"]] * n, fl["iters"],
+                                                 [fl["edges"]] * n, precision=self.precision)
+
+    def decompose(self, f):
+        """f [B, 3, H, W] float32 -> dict(bands [B,4,3,H,W], residual [B,3,H,W]
+        float32, source ['surrogate' | 'plain'] per image, identity_error)."""
+        out = self.net.forward(f)
+        err = tvspec_net_identity_error(f, out).cpu().numpy()
+        bands, res = split_output(out)
+        bands, res = bands.clone(), res.clone()
+        src = ["surrogate"] * f.shape[0]
+        fb = [i for i in range(f.shape[0]) if not (err[i] <= self.threshold)]
+        jd = []
+        if self.judge_every > 0:
+            jd = [i for i in range(f.shape[0]) if (self.count + i) % self.judge_every == 0 and i not in fb]
+        self.count += f.shape[0]
+        todo = fb + jd
+        if todo:
+            idx = torch.tensor(todo, device=f.device)
+            plain = self._plain(f.index_select(0, idx))
+            for i, o in zip(todo, plain):
+                if i in fb:
+                    bands[i].copy_(o["bands"])
+                    res[i].copy_(o["residual"])
+                    src[i] = "plain"
+                else:
+                    one = out[i:i + 1]
+                    self.judged.append(band_errors(one, o["bands"][None], o["residual"][None]))
+        self.fallbacks += len(fb)
+        return {"bands": bands, "residual": res, "source": src, "identity_error": err}
+
+
+def timed(fn, *a, **k):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn(*a, **k)
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0

@@ -14,11 +14,13 @@ and its output in float32.  The oracle runs with the same storage
 roundings (its act/out/grad hooks), so both sides take the same ReLU and
 max-pooling decisions; what remains is float32 accumulation against float64
 (relative ~1e-6 per sum), which moves a stored value across a bfloat16
-rounding boundary only rarely.  Output and loss are compared within 1e-2
-relative L2, every parameter gradient within 3e-2.  Without the hooks
-(pure float64 oracle) the first layer's gradient differs by ~15%: ties
-in bfloat16 max-pooling windows and ReLU inputs near zero route gradients
-differently.
+rounding boundary only rarely, but then by one bfloat16 step (2^-8
+relative), and the change propagates.  Output and loss are compared within
+1e-2 relative L2.  A parameter gradient entry is a sum over all pixels of
+terms of both signs that largely cancel (on the first layer its size is a
+few per cent of the sum of the terms' sizes), so its error is judged
+against that sum of sizes, sum_p |dz||x| (the oracle reports it): within
+2e-2 in L2 norm, per layer.
 """
 import numpy as np
 import pytest
@@ -101,9 +103,11 @@ def test_conv3x3_wgrad_exact(nn, B, H, W, Cin, Cout):
 
 
 def oracle_params(p, nn):
+    """The parameters as the kernels use them: weights rounded to bfloat16
+    from the float32 master copy, biases float32."""
     out = {}
     for name, (w, b) in nn.split_params(p).items():
-        out[name] = (w.astype(np.float64), b.astype(np.float64))
+        out[name] = (to_bf16_np(w.astype(np.float64)), b.astype(np.float64))
     return out
 
 
@@ -171,21 +175,44 @@ def test_network_loss_and_gradients_against_oracle(nn, small_net):
     t = to_f32_np(np.concatenate([bands.reshape(2, 12, 32, 32), res], axis=1).transpose(0, 2, 3, 1))
     ref_loss, dy = orc_nn.nmse_loss(y, t, 5)
     assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
-    ref_g = model.backward(params, cache, to_bf16_np(dy))
+    scales = {}
+    ref_g = model.backward(params, cache, to_bf16_np(dy), scales=scales)
     gs = nn.split_params(g)
     for name, _, _ in nn.LAYERS:
-        assert rel(gs[name][0], ref_g[name][0]) < 3e-2, (name, rel(gs[name][0], ref_g[name][0]))
-        assert rel(gs[name][1], ref_g[name][1]) < 3e-2, (name, rel(gs[name][1], ref_g[name][1]))
+        for k in (0, 1):
+            err = np.linalg.norm(gs[name][k] - ref_g[name][k]) / np.linalg.norm(scales[name][k])
+            assert err < 2e-2, (name, k, err, rel(gs[name][k], ref_g[name][k]))
 
 
 def test_training_reduces_the_loss(nn):
+    """From the zero output layer (loss 1 per band) the network learns
+    targets that are a fixed linear function of the image."""
     net = nn.Net(32, 32, 2, seed=9)
-    f, bands, res = inputs(3)
-    ft, bt, rt = (torch.from_numpy(a).to(DEV) for a in (f, bands, res))
+    f, _, _ = inputs(3)
+    c = (f - 0.5).astype(np.float64)
+    bands = np.stack([0.1 * (j + 1) * c for j in range(4)], axis=1)
+    res = f.astype(np.float64) - bands.sum(axis=1)
+    ft, bt, rt = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (f, bands, res))
     first = net.train_step(ft, bt, rt, 1e-3)
-    for _ in range(60):
+    assert abs(first - 1.0) < 1e-6  # zero output layer
+    for _ in range(100):
         last = net.train_step(ft, bt, rt, 1e-3)
     assert np.isfinite(last) and last < 0.5 * first, (first, last)
+    net.close()
+
+
+def test_output_scale_is_exact(nn):
+    net = nn.Net(16, 16, 1, seed=6)
+    p = net.get_params()
+    net.set_params(p + 0.05 * np.random.default_rng(1).standard_normal(p.size).astype(np.float32))
+    f = torch.from_numpy(inputs(7, B=1, H=16, W=16)[0]).to(DEV)
+    a = net.forward(f).cpu().numpy()
+    s = np.linspace(0.01, 2.0, 15).astype(np.float32)
+    net.set_output_scale(s)
+    b = net.forward(f).cpu().numpy()
+    assert np.array_equal(b, a * s[None, :, None, None])
+    with pytest.raises(nn.TvspecError):
+        net.set_output_scale(np.zeros(15, np.float32))
     net.close()
 
 
@@ -193,6 +220,8 @@ def test_adam_step_against_oracle(nn):
     """One training step moves every parameter by Adam's first step,
     lr * g / (|g| + eps) (float32 update of the float32 master weights)."""
     net = nn.Net(16, 16, 1, seed=4)
+    p = net.get_params()
+    net.set_params(p + 0.05 * np.random.default_rng(2).standard_normal(p.size).astype(np.float32))
     f, bands, res = inputs(4, B=1, H=16, W=16)
     ft, bt, rt = (torch.from_numpy(a).to(DEV) for a in (f, bands, res))
     p0 = net.get_params()
