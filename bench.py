@@ -160,6 +160,89 @@ SERVING = {
 }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
+
+
+def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side=1024, seed=11):
+    """The learned surrogate end to end on the surrogate workload: training
+    data decomposed by the batched plain path (3 x 256^2 shape images,
+    dt 0.005, K 100, 150 iterations, 4 dyadic bands), `steps` Adam steps
+    (batch 16, lr 1e-3), band errors on held-out images, inference
+    throughput against the bf16 MFMA peak, serving with identity-error
+    fallback, and the surrogate against the plain path at mega_side^2."""
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import nn, surrogate as S
+
+    dev = torch.device("cuda:0")
+    rec = {"workload": "3x256x256 synthetic shape images, encoder-decoder 48-96-192-384, 4 bands x 3 + residual; "
+                       "targets from the plain path dt 0.005, K 100, 150 iterations",
+           "train_images": n_train, "test_images": test_images, "steps": steps, "batch": batch, "lr": lr}
+    t0 = time.perf_counter()
+    imgs = S.make_images(n_train + test_images, 256, 20000 + seed)
+    f = torch.from_numpy(imgs).to(dev)
+    rec["data_gen_s"] = time.perf_counter() - t0
+    (bands, res), dt = S.timed(S.decompose_dataset, f)
+    px = (n_train + test_images) * 256 * 256
+    rec["plain_batch_256"] = {"images": n_train + test_images, "s": dt, "MPix_per_s": px / 1e6 / dt}
+    print("bench: surrogate training data ready (%.1f s)" % dt, file=sys.stderr, flush=True)
+    ftr, btr, rtr = f[:n_train], bands[:n_train], res[:n_train]
+    fte, bte, rte = f[n_train:], bands[n_train:], res[n_train:]
+    net = nn.Net(256, 256, batch, seed=seed)
+    net.set_output_scale(S.output_scales(btr, rtr))
+    losses = []
+    t1 = time.perf_counter()
+    for a in range(0, steps, 250):
+        losses += S.train(net, ftr, btr, rtr, min(250, steps - a), batch, lr, seed=seed + a)
+        print("bench: surrogate step %d loss %.4f" % (len(losses), float(np.mean(losses[-25:]))), file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t1
+    rec["train"] = {"s": tt, "ms_per_step": tt * 1e3 / max(steps, 1), "loss_first": losses[0] if losses else None,
+                    "loss_last25": float(np.mean(losses[-25:])) if losses else None}
+    out = torch.cat([net.forward(fte[i:i + batch].contiguous()) for i in range(0, test_images, batch)])
+    rec["band_rel_l1"] = S.band_errors(out, bte, rte)
+    err = nn.tvspec_net_identity_error(fte.contiguous(), out).cpu().numpy()
+    rec["identity_error"] = {"mean": float(err.mean()), "max": float(err.max())}
+    # inference throughput (batch of 16 at 256^2)
+    x = fte[:batch].contiguous()
+    o = net.forward(x)
+    reps = 20
+    _, ti = S.timed(lambda: [net.forward(x, o) for _ in range(reps)])
+    ms = ti * 1e3 / reps
+    flops = S.conv_flops(256, 256) * batch
+    achieved = flops / (ms / 1e3) / 1e12
+    rec["inference_256"] = {"batch": batch, "ms": ms, "MPix_per_s": batch * 65536 / 1e6 / (ms / 1e3),
+                            "channel_MPix_per_s": 3 * batch * 65536 / 1e6 / (ms / 1e3)}
+    rec["roofline"] = {"kernel": "network forward (k_conv3x3, bf16 MFMA)", "bound": "mfma", "achieved": achieved,
+                       "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                       "flops_per_image": S.conv_flops(256, 256), "traffic": None}
+    # serving with fallback on the held-out images
+    svc = S.SurrogateService(net, threshold=1e-2, judge_every=8)
+    _, ts = S.timed(lambda: [svc.decompose(fte[i:i + batch].contiguous()) for i in range(0, test_images, batch)])
+    judged = svc.judged
+    rec["service_256"] = {"threshold": 1e-2, "requests": test_images, "fallbacks": svc.fallbacks,
+                          "judged": len(judged), "s": ts, "MPix_per_s": test_images * 65536 / 1e6 / ts,
+                          "judged_all_bands_rel_l1": float(np.mean([j["all_bands"] for j in judged])) if judged
+                          else None}
+    # surrogate vs plain at mega_side^2
+    big = nn.Net(mega_side, mega_side, 1, seed=seed)
+    big.set_params(net.get_params())
+    big.set_output_scale(net.output_scale)
+    fb = torch.from_numpy(S.make_images(1, mega_side, 30000 + seed)).to(dev)
+    ob = big.forward(fb)
+    _, tf = S.timed(lambda: [big.forward(fb, ob) for _ in range(5)])
+    (pb, pr), tp = S.timed(S.decompose_dataset, fb)
+    mp = mega_side * mega_side / 1e6
+    rec["mega"] = {"side": mega_side, "surrogate_ms": tf * 1e3 / 5, "surrogate_MPix_per_s": mp / (tf / 5),
+                   "plain_ms": tp * 1e3, "plain_MPix_per_s": mp / tp, "speedup": tp / (tf / 5),
+                   "band_rel_l1": S.band_errors(ob, pb, pr),
+                   "identity_error": float(nn.tvspec_net_identity_error(fb, ob).item())}
+    net.close()
+    big.close()
+    return rec
+
+
 def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
     """The serving workload through the server: first a burst of `burst`
     requests submitted at once (sustainable throughput), then n_req requests
@@ -290,6 +373,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--pdhg-steps", type=int, default=3,
                     help="also time this many decompositions with the primal-dual solver (0 = skip)")
+    ap.add_argument("--sur-train-images", type=int, default=1024,
+                    help="training images of the learned surrogate (0 = skip the surrogate)")
+    ap.add_argument("--sur-steps", type=int, default=1500, help="Adam steps of the surrogate's training")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -424,6 +510,10 @@ def main():
         rec["serving"] = serving_bench(args.serve_requests, args.serve_rate, args.serve_burst,
                                        args.serve_budget_gb, args.precision)
         print("bench: serving pass done", file=sys.stderr, flush=True)
+
+    if args.sur_train_images > 0:
+        rec["surrogate"] = surrogate_block(args.sur_train_images, args.sur_steps)
+        print("bench: surrogate pass done", file=sys.stderr, flush=True)
 
     # the host entry point (host buffers, PCIe-inclusive), once, for reference
     t1 = time.perf_counter()

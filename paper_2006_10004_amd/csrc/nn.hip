@@ -11,13 +11,14 @@
 // rows 4(l / 16) .. +3.
 //
 //   k_conv3x3      forward (and the input gradient, on flipped, transposed
-//                  weights): a workgroup of 4 waves covers 128 pixels x 64
-//                  output channels; each wave 32 pixels x 64 channels as
-//                  2 x 4 MFMA tiles, operands loaded straight from global
-//                  memory (the 9 taps re-read neighbouring pixels through the
-//                  caches); bias, ReLU or a ReLU mask fused in the epilogue.
+//                  weights): a workgroup of 4 waves covers 256 pixels x 16 NF
+//                  output channels (NF = 6, 3 or 1 to fit 96-, 48- and
+//                  16-channel layers); the weight tile goes through LDS,
+//                  activations straight from global memory one step ahead;
+//                  bias, ReLU, a ReLU mask or an output scale fused in the
+//                  epilogue.
 //   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
-//                  64 output channels x 64 values of k over a range of
+//                  64 output channels x 128 values of k over a range of
 //                  pixels, stages 64-pixel chunks of dY and of the shifted X
 //                  in LDS transposed (k-major), so MFMA operands are 16-byte
 //                  LDS reads; per-range partial sums are added in a fixed
@@ -63,25 +64,37 @@ __device__ __forceinline__ bf16x8 zero8()
 // Epilogue: + bias[o] (bias != nullptr), max(., 0) (relu), zero where
 // mask[p][o] <= 0 (mask != nullptr), times oscale[o] (oscale != nullptr);
 // stored as bf16 or f32.
-template <bool F32OUT>
+//
+// A workgroup (4 waves) covers 256 pixels x NF*16 output channels; each
+// wave 64 pixels (4 row fragments) x NF column fragments, 4 NF MFMAs per
+// step of 32 values of k.  The weight tile of a step (NF*16 channels x 32 k)
+// is shared by the 4 waves through LDS, double-buffered (one barrier per
+// step); each wave's activation fragments are its own and come straight
+// from global memory, loaded one step ahead.
+constexpr int kConvPix = 256;  // pixels per workgroup
+constexpr int kBPitch = 40;    // LDS row pitch of the weight tile (32 k + 8)
+
+template <bool F32OUT, int NF>
 __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
                                                 const float *__restrict__ bias, const __bf16 *__restrict__ mask,
                                                 const float *__restrict__ oscale, void *__restrict__ Y, int B,
                                                 int H, int W, int Cin, int Cout, int relu)
 {
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NF * 16 * kBPitch];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
     const long long P = (long long)B * H * W;
-    const long long p0 = (long long)blockIdx.x * 128 + wave * 32;
-    const int co0 = blockIdx.y * 64;
+    const long long p0 = (long long)blockIdx.x * kConvPix + wave * 64;
+    const int co0 = blockIdx.y * (NF * 16);
     const int K = 9 * Cin;
+    const int nks = (K + 31) / 32;
 
-    int pb[2], py[2], px[2];
-    bool pv[2];
+    int pb[4], py[4], px[4];
+    bool pv[4];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const long long p = p0 + r * 16 + r16;
         pv[r] = p < P;
         const long long q = pv[r] ? p : 0;
@@ -90,73 +103,97 @@ __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, co
         py[r] = rem / W;
         px[r] = rem - py[r] * W;
     }
-    const __bf16 *wrow[4];
-    bool wv[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int co = co0 + c * 16 + r16;
-        wv[c] = co < Cout;
-        wrow[c] = Wt + (size_t)(wv[c] ? co : 0) * K;
-    }
 
-    floatx4 acc[2][4];
+    // weight-tile staging: chunk c = t + 256 i is row c / 4 (output channel
+    // co0 + c / 4), 8 values of k at (c % 4) * 8 of the step
+    constexpr int kChunks = NF * 16 * 4;
+    constexpr int kCPT = (kChunks + kT - 1) / kT;
+    auto load_b = [&](int ks, bf16x8 *v) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+        for (int i = 0; i < kCPT; ++i) {
+            const int c = threadIdx.x + i * kT;
+            v[i] = zero8();
+            if (c < kChunks) {
+                const int co = co0 + (c >> 2);
+                const int k = ks * 32 + (c & 3) * 8;
+                if (co < Cout && k < K)
+                    v[i] = *(const bf16x8 *)(Wt + (size_t)co * K + k);
+            }
+        }
+    };
+    auto store_b = [&](int buf, const bf16x8 *v) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    // this lane's k = ks * 32 + 8 g: tap and channel, advanced incrementally
-    int tap = (8 * g) / Cin;
-    int ch = 8 * g - tap * Cin;
-    const int nks = (K + 31) / 32;
-    for (int ks = 0; ks < nks; ++ks) {
+        for (int i = 0; i < kCPT; ++i) {
+            const int c = threadIdx.x + i * kT;
+            if (c < kChunks)
+                *(bf16x8 *)(&sB[buf][(c >> 2) * kBPitch + (c & 3) * 8]) = v[i];
+        }
+    };
+    // this lane's activation fragments of step ks (k = 32 ks + 8 g)
+    auto load_a = [&](int ks, bf16x8 *a) {
         const int k = ks * 32 + 8 * g;
-        bf16x8 a[2], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            a[r] = zero8();
         if (k < K) {
+            const int tap = k / Cin;
+            const int ch = k - tap * Cin;
             const int dy = tap / 3 - 1;
             const int dx = tap - (tap / 3) * 3 - 1;
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
+            for (int r = 0; r < 4; ++r) {
                 const int yy = py[r] + dy;
                 const int xx = px[r] + dx;
                 if (pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W)
                     a[r] = *(const bf16x8 *)(X + ((size_t)((size_t)pb[r] * H + yy) * W + xx) * Cin + ch);
-                else
-                    a[r] = zero8();
             }
+        }
+    };
+
+    floatx4 acc[4][NF];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                b[c] = wv[c] ? *(const bf16x8 *)(wrow[c] + k) : zero8();
-        } else {
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
-                a[r] = zero8();
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                b[c] = zero8();
+        for (int c = 0; c < NF; ++c)
+            acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    bf16x8 vb[kCPT], a[4], an[4];
+    load_b(0, vb);
+    store_b(0, vb);
+    load_a(0, a);
+    __syncthreads();
+    for (int ks = 0; ks < nks; ++ks) {
+        const int cur = ks & 1;
+        const bool more = ks + 1 < nks;
+        if (more) {
+            load_b(ks + 1, vb);
+            load_a(ks + 1, an);
         }
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < NF; ++c) {
+            const bf16x8 bfr = *(const bf16x8 *)(&sB[cur][(c * 16 + r16) * kBPitch + 8 * g]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
-        ch += 32;
-        while (ch >= Cin) {
-            ch -= Cin;
-            ++tap;
+            for (int r = 0; r < 4; ++r)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
         }
+        if (more) {
+            store_b(cur ^ 1, vb);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                a[r] = an[r];
+        }
+        __syncthreads();
     }
 
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int c = 0; c < NF; ++c) {
+        const int co = co0 + c * 16 + r16;
+        if (co >= Cout)
+            continue;
+        const float bv = bias ? bias[co] : 0.f;
+        const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int co = co0 + c * 16 + r16;
-            if (co >= Cout)
-                continue;
-            const float bv = bias ? bias[co] : 0.f;
-            const float sv = oscale ? oscale[co] : 1.f;
+        for (int r = 0; r < 4; ++r) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long long p = p0 + r * 16 + 4 * g + i;
@@ -197,43 +234,58 @@ __global__ __launch_bounds__(kT) void k_flip_transpose(const __bf16 *__restrict_
 constexpr int kWChunk = 64;             // pixels per LDS stage
 constexpr int kWPitch = kWChunk + 8;    // LDS row pitch (elements), 16-byte aligned rows
 
+constexpr int kWK = 128;  // values of k per workgroup tile
+
+// Column of pixel `col` (0..63) in LDS row `row` of a transposed staging
+// tile: each group of 8 rows is rotated by 8 (row / 8 mod 8) columns, so the
+// 8 two-byte stores of one instruction (rows 8 apart, same column) fall in
+// different banks; 8 consecutive pixels stay consecutive and 16-byte
+// aligned for the MFMA operand reads.
+__device__ __forceinline__ int swz(int row, int col) { return (col + (((row >> 3) & 7) << 3)) & (kWChunk - 1); }
+
 // part[s][o][k] = sum over pixels of range s of dY[p][o] * A[p][k], for the
-// 64 x 64 tile (o0, k0) of (Cout, 9 Cin).  Range s covers chunks
+// 64 x kWK tile (o0, k0) of (Cout, 9 Cin); with bpart != nullptr the
+// workgroups of the first k tile also write bpart[s][o] = sum of dY[p][o]
+// over the range (the bias gradient's partial sums).  Range s covers chunks
 // [s * cps, (s + 1) * cps) of kWChunk pixels.
 __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
-                                              float *__restrict__ part, int B, int H, int W, int Cin, int Cout,
-                                              int cps)
+                                              float *__restrict__ part, float *__restrict__ bpart, int B, int H,
+                                              int W, int Cin, int Cout, int cps)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sA[64 * kWPitch]; // [o][pixel]
-    __shared__ __attribute__((aligned(16))) __bf16 sB[64 * kWPitch]; // [k][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sA[64 * kWPitch];  // [o][pixel]
+    __shared__ __attribute__((aligned(16))) __bf16 sB[kWK * kWPitch]; // [k][pixel]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
     const int K = 9 * Cin;
-    const int k0 = blockIdx.x * 64;
+    const int k0 = blockIdx.x * kWK;
     const int o0 = blockIdx.y * 64;
     const int s = blockIdx.z;
     const long long P = (long long)B * H * W;
     const long long HW = (long long)H * W;
+    const bool do_bias = bpart != nullptr && blockIdx.x == 0;
 
-    floatx4 acc[4];
+    floatx4 acc[kWK / 16];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < kWK / 16; ++j)
         acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
 
-    // staging roles: thread t handles pixel t / 8 (+32) and group t % 8 of 8
-    // channels (dY) or 8 values of k (X)
-    const int sp = threadIdx.x >> 3;
-    const int sg = threadIdx.x & 7;
-    const int ko = k0 + sg * 8;       // this thread's 8 values of k
+    // staging roles: dY, thread t: pixel t / 8 (+32), channels (t % 8) * 8;
+    // X, thread t: pixel t / 16 (+16, +32, +48), k values (t % 16) * 8
+    const int spa = threadIdx.x >> 3;
+    const int sga = threadIdx.x & 7;
+    const int oo = o0 + sga * 8;
+    const bool oval = oo < Cout;
+    const int spb = threadIdx.x >> 4;
+    const int sgb = threadIdx.x & 15;
+    const int ko = k0 + sgb * 8;
     const bool kval = ko < K;
     const int tap = kval ? ko / Cin : 0;
     const int ch = kval ? ko - tap * Cin : 0;
     const int dy = tap / 3 - 1;
     const int dx = tap - (tap / 3) * 3 - 1;
-    const int oo = o0 + sg * 8;
-    const bool oval = oo < Cout;
 
     for (int chunk = 0; chunk < cps; ++chunk) {
         const long long pbase = ((long long)s * cps + chunk) * kWChunk;
@@ -241,42 +293,58 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
             break;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int pl = sp + 32 * h;
+            const int pl = spa + 32 * h;
             const long long p = pbase + pl;
-            bf16x8 va = zero8(), vb = zero8();
-            if (p < P) {
-                if (oval)
-                    va = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
-                if (kval) {
-                    const int b = (int)(p / HW);
-                    const int rem = (int)(p - (long long)b * HW);
-                    const int yy = rem / W + dy;
-                    const int xx = rem - (rem / W) * W + dx;
-                    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                        vb = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
-                }
+            bf16x8 va = zero8();
+            if (p < P && oval)
+                va = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                sA[(sga * 8 + j) * kWPitch + swz(sga * 8 + j, pl)] = va[j];
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int pl = spb + 16 * h;
+            const long long p = pbase + pl;
+            bf16x8 vb = zero8();
+            if (p < P && kval) {
+                const int b = (int)(p / HW);
+                const int rem = (int)(p - (long long)b * HW);
+                const int yy = rem / W + dy;
+                const int xx = rem - (rem / W) * W + dx;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    vb = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                sA[(sg * 8 + j) * kWPitch + pl] = va[j];
-                sB[(sg * 8 + j) * kWPitch + pl] = vb[j];
-            }
+            for (int j = 0; j < 8; ++j)
+                sB[(sgb * 8 + j) * kWPitch + swz(sgb * 8 + j, pl)] = vb[j];
         }
         __syncthreads();
+        if (do_bias && threadIdx.x < 64) {
+#pragma unroll
+            for (int q = 0; q < kWChunk; q += 8) {
+                const bf16x8 v = *(const bf16x8 *)(sA + threadIdx.x * kWPitch + q);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    bacc += (float)v[j];
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < kWChunk; kk += 32) {
-            const bf16x8 a = *(const bf16x8 *)(sA + (wave * 16 + r16) * kWPitch + kk + 8 * g);
+            const int ra = wave * 16 + r16;
+            const bf16x8 av = *(const bf16x8 *)(sA + ra * kWPitch + swz(ra, kk + 8 * g));
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bf16x8 b = *(const bf16x8 *)(sB + (j * 16 + r16) * kWPitch + kk + 8 * g);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            for (int j = 0; j < kWK / 16; ++j) {
+                const int rb = j * 16 + r16;
+                const bf16x8 bv = *(const bf16x8 *)(sB + rb * kWPitch + swz(rb, kk + 8 * g));
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
             }
         }
         __syncthreads();
     }
     float *out = part + (size_t)s * Cout * K;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kWK / 16; ++j) {
         const int k = k0 + j * 16 + r16;
         if (k >= K)
             continue;
@@ -287,6 +355,8 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
                 out[(size_t)o * K + k] = acc[j][i];
         }
     }
+    if (do_bias && threadIdx.x < 64 && o0 + (int)threadIdx.x < Cout)
+        bpart[(size_t)s * Cout + o0 + threadIdx.x] = bacc;
 }
 
 // out[q] = sum_s part[s * n + q], s = 0 .. ns-1 in order.
@@ -298,21 +368,6 @@ __global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ pa
         for (int s = 0; s < ns; ++s)
             a += part[(size_t)s * n + q];
         out[q] = a;
-    }
-}
-
-// part[s][o] = sum of dY[p][o] over the pixels of range s (cps pixels each).
-__global__ __launch_bounds__(kT) void k_bias_partial(const __bf16 *__restrict__ dY, long long P, int Cout,
-                                                     long long cps, float *__restrict__ part)
-{
-    const int s = blockIdx.y;
-    const long long pa = s * cps;
-    const long long pe = pa + cps < P ? pa + cps : P;
-    for (int o = blockIdx.x * kT + threadIdx.x; o < Cout; o += gridDim.x * kT) {
-        float a = 0.f;
-        for (long long p = pa; p < pe; ++p)
-            a += (float)dY[(size_t)p * Cout + o];
-        part[(size_t)s * Cout + o] = a;
     }
 }
 
@@ -540,14 +595,15 @@ __global__ __launch_bounds__(kT) void k_loss_partial(const float *__restrict__ o
     }
 }
 
-// nd[b][j][2] = totals (fixed order); loss[0] = (1/(5B)) sum num/den.
-__global__ __launch_bounds__(64) void k_loss_total(const float *__restrict__ part, int B, int nblk,
+// nd[b][j][2] = totals (fixed order); loss[0] = (1/(5B)) sum num/den.  One
+// block: thread t totals the pairs t, t + 256, ...; the loss terms are then
+// added in a fixed order.
+__global__ __launch_bounds__(kT) void k_loss_total(const float *__restrict__ part, int B, int nblk,
                                                    float *__restrict__ nd, float *__restrict__ loss)
 {
-    if (threadIdx.x != 0)
-        return;
+    __shared__ double sl[kT];
     double l = 0.0;
-    for (int bj = 0; bj < B * kGroups; ++bj) {
+    for (int bj = threadIdx.x; bj < B * kGroups; bj += kT) {
         double a = 0.0, d = 0.0;
         for (int k = 0; k < nblk; ++k) {
             a += part[((size_t)bj * nblk + k) * 2];
@@ -557,7 +613,14 @@ __global__ __launch_bounds__(64) void k_loss_total(const float *__restrict__ par
         nd[2 * bj + 1] = (float)d;
         l += d > 0.0 ? a / d : 0.0;
     }
-    loss[0] = (float)(l / (double)(B * kGroups));
+    sl[threadIdx.x] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kT; ++i)
+            t += sl[i];
+        loss[0] = (float)(t / (double)(B * kGroups));
+    }
 }
 
 // do = 2 (o - t) / (den_bj 5 B) times the output scale of the channel (the
@@ -697,17 +760,38 @@ int ensure(void **p, size_t *have, size_t bytes)
     return TVSPEC_OK;
 }
 
+template <int NF>
+void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
+                 int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+{
+    const long long P = (long long)B * H * W;
+    const dim3 grid((unsigned)((P + kConvPix - 1) / kConvPix), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
+    if (f32)
+        hipLaunchKernelGGL((k_conv3x3<true, NF>), grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin,
+                           Cout, relu);
+    else
+        hipLaunchKernelGGL((k_conv3x3<false, NF>), grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin,
+                           Cout, relu);
+}
+
+// Column fragments per wave: 6 (96 channels) unless the layer is narrower.
+int conv_nf(int Cout)
+{
+    if (Cout <= 16)
+        return 1;
+    if (Cout <= 48)
+        return 3;
+    return 6;
+}
+
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
              const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr)
 {
-    const long long P = (long long)B * H * W;
-    const dim3 grid((unsigned)((P + 127) / 128), (unsigned)((Cout + 63) / 64));
-    if (f32)
-        hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin, Cout,
-                           relu);
-    else
-        hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin, Cout,
-                           relu);
+    switch (conv_nf(Cout)) {
+    case 1: conv_launch<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 3: conv_launch<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    default: conv_launch<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -726,7 +810,7 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
 {
     const long long P = (long long)B * H * W;
     const int K = 9 * Cin;
-    const int tk = (K + 63) / 64, to = (Cout + 63) / 64;
+    const int tk = (K + kWK - 1) / kWK, to = (Cout + 63) / 64;
     const long long chunks = (P + kWChunk - 1) / kWChunk;
     // enough ranges to give the device ~2048 workgroups
     long long ns = 2048 / ((long long)tk * to);
@@ -735,16 +819,14 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
     const int cps = (int)((chunks + ns - 1) / ns);
     ns = (chunks + cps - 1) / cps;
     const size_t n = (size_t)Cout * K;
-    const long long bcps = (P + 255) / 256;
-    const size_t need = ((size_t)ns * n + (size_t)256 * Cout) * sizeof(float);
+    const size_t need = ((size_t)ns * n + (size_t)ns * Cout) * sizeof(float);
     TVSPEC_TRY(ensure((void **)&wk.part, &wk.part_bytes, need));
-    hipLaunchKernelGGL(k_wgrad, dim3(tk, to, (unsigned)ns), dim3(kT), 0, st, x, dy, wk.part, B, H, W, Cin, Cout, cps);
+    float *bp = db ? wk.part + (size_t)ns * n : nullptr;
+    hipLaunchKernelGGL(k_wgrad, dim3(tk, to, (unsigned)ns), dim3(kT), 0, st, x, dy, wk.part, bp, B, H, W, Cin, Cout,
+                       cps);
     hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for((long long)n)), dim3(kT), 0, st, wk.part, (int)ns, n, dw);
-    if (db) {
-        float *bp = wk.part + (size_t)ns * n;
-        hipLaunchKernelGGL(k_bias_partial, dim3((Cout + kT - 1) / kT, 256), dim3(kT), 0, st, dy, P, Cout, bcps, bp);
-        hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(Cout)), dim3(kT), 0, st, bp, 256, (size_t)Cout, db);
-    }
+    if (db)
+        hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(Cout)), dim3(kT), 0, st, bp, (int)ns, (size_t)Cout, db);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -890,7 +972,7 @@ int loss_and_grad(tvspec_net *n, const double *bands, const double *res, int B, 
     const long long HW = (long long)n->H * n->W;
     hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, n->tgt, B, HW);
     hipLaunchKernelGGL(k_loss_partial, dim3(n->lblk, B), dim3(kT), 0, st, n->out, n->tgt, HW, n->lpart);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(kT), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
     hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd,
                        n->oscale, B, HW, n->dout);
     HIP_TRY(hipGetLastError());
