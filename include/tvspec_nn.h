@@ -17,7 +17,11 @@
  *   channels, two 3x3 conv + ReLU; a final 3x3 conv (no activation) to
  *   out_channels = 4 bands x 3 colour channels + 3 residual channels = 15.
  *   The first layer sees the image as 2 f - 1 (centred; images lie in
- *   [0, 1]); this fixed map is part of the network.
+ *   [0, 1]); this fixed map is part of the network.  The residual outputs
+ *   are f plus the last layer's residual channels (a skip from the input, as
+ *   in the residual learning of DnCNN, the network the paper builds on): the
+ *   residual is most of the image and the layer only learns its difference
+ *   from f, which is minus the sum of the bands.
  *
  * Arithmetic: bfloat16 weights and activations, float32 accumulation in
  * the matrix cores (v_mfma_f32_16x16x32_bf16), float32 biases, outputs,
@@ -88,7 +92,8 @@ typedef struct tvspec_net tvspec_net;
  * Create the network for images of H x W (multiples of 8) and batches of up
  * to max_batch, on the current device, with He-normal weights drawn from a
  * counter-based generator seeded by `seed`, zero biases and a zero output
- * layer (so training starts from zero bands, loss 1 per band), and output
+ * layer (so training starts from zero bands and residual f, loss 1 per
+ * group), and output
  * scales of 1.  Activations, gradients and Adam state for max_batch are
  * allocated here.
  */
@@ -116,7 +121,8 @@ TVSPEC_API int tvspec_net_set_output_scale(tvspec_net *net, const float *scale);
 /*
  * Forward pass.  f device float32 [B][3][H][W]; out device float32
  * [B][15][H][W] (channel 3j + c = band j of colour c for j < 4, 12 + c =
- * residual of colour c).  B <= max_batch.
+ * residual of colour c, which is f + scale * the last layer's channel).
+ * B <= max_batch.
  */
 TVSPEC_API int tvspec_net_forward(tvspec_net *net, const float *f, int B, float *out, void *stream);
 
@@ -126,7 +132,11 @@ TVSPEC_API int tvspec_net_forward(tvspec_net *net, const float *f, int B, float 
  * float64 [B][3][H][W], the layouts of tvspec_decompose_batch_dev with four
  * bands), backward, one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8).
  * The loss groups the output into 5 bands of 3 channels (the 4 bands and
- * the residual):  (1/(5B)) sum_b sum_j ||o_bj - t_bj||^2 / ||t_bj||^2.
+ * the residual):  (1/(5B)) sum_b sum_j ||o_bj - t_bj||^2 / ||t_bj||^2 with
+ * t_bj the band for j < 4; for the residual group the numerator is
+ * ||o - residual||^2 and the denominator ||residual - f||^2, the size of what
+ * the residual's learned part has to carry.  A group with a zero
+ * denominator contributes 0.
  * *loss (host) receives the batch loss; the call waits for the stream.
  */
 TVSPEC_API int tvspec_net_train_step(tvspec_net *net, const float *f, const double *bands,

@@ -21,6 +21,13 @@ connections up).  Everything below is written from those definitions:
                   its gradient in o
   adam_step       Kingma and Ba's update with bias correction
   UNetOracle      the encoder-decoder's forward and backward passes
+  surrogate_input / surrogate_output / surrogate_target
+                  the surrogate's maps around the encoder-decoder: the image
+                  enters as 2 f - 1; output channel c is scale[c] times the
+                  last layer's channel, and the residual channels add f (a
+                  skip from the input, the residual learning of DnCNN, which
+                  the paper's network is based on); the last layer is trained
+                  towards the bands and r - f
 
 Each tensor is a numpy array in float64, images channels-last [B, H, W, C].
 """
@@ -218,3 +225,38 @@ class UNetOracle:
             d = layer(lb, d)
             d = layer(la, d)
         return g
+
+
+def surrogate_input(f):
+    """Images f [B, 3, H, W] in [0, 1] -> the network's input 2 f - 1,
+    channels last [B, H, W, 3]."""
+    return np.transpose(2.0 * np.asarray(f, dtype=np.float64) - 1.0, (0, 2, 3, 1))
+
+
+def surrogate_output(y, f, scale):
+    """Last layer's output y [B, H, W, 15] -> decomposition [B, 15, H, W]:
+    channel c is scale[c] y_c; channels 3j + c (j < 4) are band j of colour c,
+    and 12 + c is the residual of colour c, f_c + scale y."""
+    out = np.transpose(np.asarray(y, dtype=np.float64) * np.asarray(scale, dtype=np.float64), (0, 3, 1, 2)).copy()
+    out[:, 12:] += np.asarray(f, dtype=np.float64)
+    return out
+
+
+def surrogate_target(f, bands, res):
+    """What the last layer (before the output scale) is trained towards,
+    [B, H, W, 15]: the bands [B, 4, 3, H, W] and r - f for the residual."""
+    B, nb, C, H, W = bands.shape
+    t = np.concatenate([np.asarray(bands, dtype=np.float64).reshape(B, nb * C, H, W),
+                        np.asarray(res, dtype=np.float64) - np.asarray(f, dtype=np.float64)], axis=1)
+    return np.transpose(t, (0, 2, 3, 1))
+
+
+def identity_error(f, out):
+    """Reconstruction-identity error of decompositions out [B, 15, H, W]
+    (Eq. (7): f = sum of bands + residual): per image, the mean over
+    channels and pixels of |f - sum_j band_j - residual|."""
+    f = np.asarray(f, dtype=np.float64)
+    out = np.asarray(out, dtype=np.float64)
+    B, C, H, W = f.shape
+    d = f - out[:, :12].reshape(B, 4, C, H, W).sum(axis=1) - out[:, 12:]
+    return np.abs(d).mean(axis=(1, 2, 3))

@@ -519,9 +519,13 @@ constexpr int kOutC = TVSPEC_NET_OUT_CHANNELS;  // 15
 constexpr int kOutPad = 16;                       // channels of the last layer's output
 constexpr int kGroups = TVSPEC_NET_BANDS + 1;     // 4 bands + residual, 3 channels each
 
-// t [P][16] float from bands [B][4][3][H][W] and residual [B][3][H][W] (float64).
+// t [P][16] float from bands [B][4][3][H][W] and residual [B][3][H][W]
+// (float64).  The residual output is f plus the last layer's channels 12..14,
+// so those channels are trained towards r - f (the sign-flipped sum of the
+// bands), computed here in float64 before the rounding.
 __global__ __launch_bounds__(kT) void k_pack_target(const double *__restrict__ bands, const double *__restrict__ res,
-                                                    float *__restrict__ t, int B, long long HW)
+                                                    const float *__restrict__ f, float *__restrict__ t, int B,
+                                                    long long HW)
 {
     const long long P = B * HW;
     for (long long p = (long long)blockIdx.x * kT + threadIdx.x; p < P; p += (long long)gridDim.x * kT) {
@@ -532,21 +536,22 @@ __global__ __launch_bounds__(kT) void k_pack_target(const double *__restrict__ b
             for (int c = 0; c < 3; ++c)
                 tp[3 * j + c] = (float)bands[((b * TVSPEC_NET_BANDS + j) * 3 + c) * HW + q];
         for (int c = 0; c < 3; ++c)
-            tp[12 + c] = (float)res[(b * 3 + c) * HW + q];
+            tp[12 + c] = (float)(res[(b * 3 + c) * HW + q] - (double)f[(b * 3 + c) * HW + q]);
         tp[15] = 0.f;
     }
 }
 
-// o [P][16] float -> out [B][15][H][W].
-__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, float *__restrict__ out, int B,
-                                                      long long HW)
+// o [P][16] float -> out [B][15][H][W], the residual channels plus f [B][3][H][W].
+__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, const float *__restrict__ f,
+                                                      float *__restrict__ out, int B, long long HW)
 {
     const long long n = B * HW * kOutC;
     for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
         const long long pix = q % HW;
         const int c = (int)((q / HW) % kOutC);
         const long long b = q / (HW * kOutC);
-        out[q] = o[(size_t)(b * HW + pix) * kOutPad + c];
+        const float v = o[(size_t)(b * HW + pix) * kOutPad + c];
+        out[q] = c >= 3 * TVSPEC_NET_BANDS ? v + f[(b * 3 + c - 3 * TVSPEC_NET_BANDS) * HW + pix] : v;
     }
 }
 
@@ -967,10 +972,10 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st)
 }
 
 // Loss of the last forward pass against bands/residual; leaves dL/dout in n->dout.
-int loss_and_grad(tvspec_net *n, const double *bands, const double *res, int B, hipStream_t st)
+int loss_and_grad(tvspec_net *n, const float *f, const double *bands, const double *res, int B, hipStream_t st)
 {
     const long long HW = (long long)n->H * n->W;
-    hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, n->tgt, B, HW);
+    hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, f, n->tgt, B, HW);
     hipLaunchKernelGGL(k_loss_partial, dim3(n->lblk, B), dim3(kT), 0, st, n->out, n->tgt, HW, n->lpart);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(kT), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
     hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd,
@@ -1277,7 +1282,7 @@ extern "C" int tvspec_net_forward(tvspec_net *net, const float *f, int B, float 
     hipStream_t st = (hipStream_t)stream;
     TVSPEC_TRY(forward(net, f, B, st));
     const long long HW = (long long)net->H * net->W;
-    hipLaunchKernelGGL(k_unpack_output, dim3(grid_for(B * HW * kOutC)), dim3(kT), 0, st, net->out, out, B, HW);
+    hipLaunchKernelGGL(k_unpack_output, dim3(grid_for(B * HW * kOutC)), dim3(kT), 0, st, net->out, f, out, B, HW);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1292,7 +1297,7 @@ extern "C" int tvspec_net_loss_grad(tvspec_net *net, const float *f, const doubl
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
     TVSPEC_TRY(forward(net, f, B, st));
-    TVSPEC_TRY(loss_and_grad(net, bands, residual, B, st));
+    TVSPEC_TRY(loss_and_grad(net, f, bands, residual, B, st));
     TVSPEC_TRY(backward(net, B, st));
     HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     if (grads)
@@ -1313,7 +1318,7 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
     TVSPEC_TRY(forward(net, f, B, st));
-    TVSPEC_TRY(loss_and_grad(net, bands, residual, B, st));
+    TVSPEC_TRY(loss_and_grad(net, f, bands, residual, B, st));
     TVSPEC_TRY(backward(net, B, st));
     net->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;

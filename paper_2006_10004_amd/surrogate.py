@@ -67,11 +67,13 @@ def decompose_dataset(f, flow=FLOW, chunk=64, precision="mixed"):
 
 def output_scales(bands, res):
     """Output scales [15]: the RMS of each band over a dataset (its three
-    colour channels share it) and of the residual."""
+    colour channels share it) and, for the residual's learned part (the
+    residual minus f, i.e. minus the sum of the bands), the RMS of the sum of
+    the bands."""
     s = np.empty(OUT_CHANNELS, np.float32)
     for j in range(BANDS):
         s[3 * j:3 * j + 3] = float(bands[:, j].pow(2).mean().sqrt())
-    s[3 * BANDS:] = float(res.pow(2).mean().sqrt())
+    s[3 * BANDS:] = float(bands.sum(dim=1).pow(2).mean().sqrt())
     return s
 
 

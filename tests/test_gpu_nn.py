@@ -158,10 +158,12 @@ def test_network_forward_against_oracle(nn, small_net):
     o = out.cpu().numpy().astype(np.float64)                          # [B,15,H,W]
     model = stored_model()
     # the network sees 2 f - 1 rounded to bfloat16
-    x = to_bf16_np(2.0 * np.transpose(f, (0, 2, 3, 1)).astype(np.float64) - 1.0)
+    x = to_bf16_np(orc_nn.surrogate_input(f))
     y, _ = model.forward(oracle_params(p, nn), x)
-    ref = np.transpose(y, (0, 3, 1, 2))
-    assert rel(o, ref) < 1e-2, rel(o, ref)
+    ref = orc_nn.surrogate_output(y, f, np.ones(15))
+    assert rel(o[:, :12], ref[:, :12]) < 1e-2, rel(o[:, :12], ref[:, :12])
+    # the residual's learned part, without the f it adds
+    assert rel(o[:, 12:] - f, ref[:, 12:] - f) < 1e-2
 
 
 def test_network_loss_and_gradients_against_oracle(nn, small_net):
@@ -170,10 +172,10 @@ def test_network_loss_and_gradients_against_oracle(nn, small_net):
     loss, g = net.loss_grad(torch.from_numpy(f).to(DEV), torch.from_numpy(bands).to(DEV),
                             torch.from_numpy(res).to(DEV))
     model = stored_model()
-    x = to_bf16_np(2.0 * np.transpose(f, (0, 2, 3, 1)).astype(np.float64) - 1.0)
+    x = to_bf16_np(orc_nn.surrogate_input(f))
     params = oracle_params(p, nn)
     y, cache = model.forward(params, x)
-    t = to_f32_np(np.concatenate([bands.reshape(2, 12, 32, 32), res], axis=1).transpose(0, 2, 3, 1))
+    t = to_f32_np(orc_nn.surrogate_target(f, bands, res))
     ref_loss, dy = orc_nn.nmse_loss(y, t, 5)
     assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
     scales = {}
@@ -186,8 +188,9 @@ def test_network_loss_and_gradients_against_oracle(nn, small_net):
 
 
 def test_training_reduces_the_loss(nn):
-    """From the zero output layer (loss 1 per band) the network learns
-    targets that are a fixed linear function of the image."""
+    """From the zero output layer (bands 0, residual f: loss 1 per group)
+    the network learns targets that are a fixed linear function of the
+    image."""
     net = nn.Net(32, 32, 2, seed=9)
     f, _, _ = inputs(3)
     c = (f - 0.5).astype(np.float64)
@@ -211,7 +214,17 @@ def test_output_scale_is_exact(nn):
     s = np.linspace(0.01, 2.0, 15).astype(np.float32)
     net.set_output_scale(s)
     b = net.forward(f).cpu().numpy()
-    assert np.array_equal(b, a * s[None, :, None, None])
+    fn = f.cpu().numpy()
+    # band channels: exactly scaled; residual: f + scale * (its learned part),
+    # up to the float32 rounding of the additions of f
+    assert np.array_equal(b[:, :12], a[:, :12] * s[None, :12, None, None])
+    # a = fl(o + f), b = fl(fl(s o) + f) for the last layer's value o: b
+    # differs from f + s (a - f) by at most 2^-24 (|b| + s |o| + s |a|)
+    sr = s[None, 12:, None, None].astype(np.float64)
+    ar, br = a[:, 12:].astype(np.float64), b[:, 12:].astype(np.float64)
+    za = ar - fn
+    bound = 2.0 ** -23 * (np.abs(br) + sr * np.abs(za) + sr * np.abs(ar))
+    assert np.all(np.abs(br - (fn + za * sr)) <= bound)
     with pytest.raises(nn.TvspecError):
         net.set_output_scale(np.zeros(15, np.float32))
     net.close()

@@ -147,3 +147,35 @@ def test_unet_backward_by_finite_differences(tiny):
         pp[name] = (w, b - e)
         fm = np.sum(net.forward(pp, x)[0] * dy)
         assert abs((fp - fm) / (2 * h) - g[name][1][0]) < 1e-5 * max(1.0, abs(fp - fm) / (2 * h)), name
+
+
+def test_surrogate_maps_reconstruction_identity_and_zero_layer():
+    """A last layer that hits its target exactly gives a decomposition that
+    satisfies f = sum of bands + residual whenever the targets do (Eq. (7));
+    a zero last layer gives bands 0, residual f and loss 1 per group; the
+    input map sends [0, 1] to [-1, 1]."""
+    B, H, W = 2, 5, 6
+    f = RNG.random((B, 3, H, W))
+    bands = 0.1 * RNG.standard_normal((B, 4, 3, H, W))
+    res = f - bands.sum(axis=1)
+    scale = np.linspace(0.5, 2.0, 15)
+    t = nn.surrogate_target(f, bands, res)
+    assert t.shape == (B, H, W, 15)
+    out = nn.surrogate_output(t / scale, f, scale)
+    assert np.allclose(out[:, :12].reshape(B, 4, 3, H, W), bands, atol=1e-15)
+    assert np.allclose(out[:, 12:], res, atol=1e-15)
+    assert np.allclose(out[:, :12].reshape(B, 4, 3, H, W).sum(axis=1) + out[:, 12:], f, atol=1e-14)
+    z = nn.surrogate_output(np.zeros((B, H, W, 15)), f, scale)
+    assert np.all(z[:, :12] == 0.0) and np.array_equal(z[:, 12:], f)
+    loss, _ = nn.nmse_loss(np.zeros_like(t), t, 5)
+    assert abs(loss - 1.0) < 1e-15
+    assert np.all(nn.identity_error(f, out) < 1e-15) and np.all(nn.identity_error(f, z) == 0.0)
+    # all-zero output: the error is the mean of |f|; a shift by d of one
+    # band's channel adds |d| / 3
+    e0 = nn.identity_error(f, np.zeros((B, 15, H, W)))
+    assert np.allclose(e0, np.abs(f).mean(axis=(1, 2, 3)), rtol=0, atol=1e-15)
+    sh = out.copy()
+    sh[:, 4] += 0.3
+    assert np.allclose(nn.identity_error(f, sh), 0.1, rtol=0, atol=1e-14)
+    x = nn.surrogate_input(np.stack([np.zeros((3, H, W)), np.ones((3, H, W))]))
+    assert x.shape == (2, H, W, 3) and np.all(x[0] == -1.0) and np.all(x[1] == 1.0)
