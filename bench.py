@@ -163,23 +163,29 @@ SERVING = {
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
 
 
-def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side=1024, seed=11):
+def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_sides=(1024, 2048), mega_requests=8,
+                    seed=11):
     """The learned surrogate end to end on the surrogate workload: training
     data decomposed by the batched plain path (3 x 256^2 shape images,
     dt 0.005, K 100, 150 iterations, 4 dyadic bands), `steps` Adam steps
     (batch 16, lr 1e-3), band errors on held-out images, inference
     throughput against the bf16 MFMA peak, serving with identity-error
-    fallback, and the surrogate against the plain path at mega_side^2."""
+    fallback; then megapixel serving: `mega_requests` images alternating
+    over mega_sides (300 shapes, radius up to 400 px), one request at a time,
+    through the surrogate service and through the plain path, with per-request
+    latency and the surrogate's band error against the plain path."""
     import numpy as np
     import torch
-    from paper_2006_10004_amd import nn, surrogate as S
+    from paper_2006_10004_amd import nn, surrogate as S, synth
 
     dev = torch.device("cuda:0")
-    rec = {"workload": "3x256x256 synthetic shape images, encoder-decoder 48-96-192-384, 4 bands x 3 + residual; "
+    rec = {"workload": "3x256x256 synthetic shape images (half 40-shape images, half crops of 1024x1024 "
+                       "300-shape images), encoder-decoder 48-96-192-384, 4 bands x 3 + residual; "
                        "targets from the plain path dt 0.005, K 100, 150 iterations",
            "train_images": n_train, "test_images": test_images, "steps": steps, "batch": batch, "lr": lr}
     t0 = time.perf_counter()
-    imgs = S.make_images(n_train + test_images, 256, 20000 + seed)
+    imgs = np.concatenate([S.make_training_images(n_train, 256, 20000 + seed),
+                           S.make_training_images(test_images, 256, 90000 + seed)])
     f = torch.from_numpy(imgs).to(dev)
     rec["data_gen_s"] = time.perf_counter() - t0
     (bands, res), dt = S.timed(S.decompose_dataset, f)
@@ -190,6 +196,7 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     fte, bte, rte = f[n_train:], bands[n_train:], res[n_train:]
     net = nn.Net(256, 256, batch, seed=seed)
     net.set_output_scale(S.output_scales(btr, rtr))
+    net.set_loss_floor(S.LOSS_FLOOR)
     losses = []
     t1 = time.perf_counter()
     for a in range(0, steps, 250):
@@ -225,21 +232,66 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
                           "judged": len(judged), "s": ts, "MPix_per_s": test_images * 65536 / 1e6 / ts,
                           "judged_all_bands_rel_l1": float(np.mean([j["all_bands"] for j in judged])) if judged
                           else None}
-    # surrogate vs plain at mega_side^2
-    big = nn.Net(mega_side, mega_side, 1, seed=seed)
-    big.set_params(net.get_params())
-    big.set_output_scale(net.output_scale)
-    fb = torch.from_numpy(S.make_images(1, mega_side, 30000 + seed)).to(dev)
-    ob = big.forward(fb)
-    _, tf = S.timed(lambda: [big.forward(fb, ob) for _ in range(5)])
-    (pb, pr), tp = S.timed(S.decompose_dataset, fb)
-    mp = mega_side * mega_side / 1e6
-    rec["mega"] = {"side": mega_side, "surrogate_ms": tf * 1e3 / 5, "surrogate_MPix_per_s": mp / (tf / 5),
-                   "plain_ms": tp * 1e3, "plain_MPix_per_s": mp / tp, "speedup": tp / (tf / 5),
-                   "band_rel_l1": S.band_errors(ob, pb, pr),
-                   "identity_error": float(nn.tvspec_net_identity_error(fb, ob).item())}
+    print("bench: surrogate 256x256 evaluation done", file=sys.stderr, flush=True)
+    rec["megapixel"] = megapixel_serving(net, mega_sides, mega_requests, seed)
     net.close()
-    big.close()
+    return rec
+
+
+def megapixel_serving(net, sides, n_req, seed):
+    """Megapixel requests served one at a time (each waited for): through the
+    surrogate service (identity-error fallback at 1e-2) and through the plain
+    path with the flow the surrogate was trained on, on the same images."""
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import nn, surrogate as S, synth
+
+    dev = torch.device("cuda:0")
+    p, scale = net.get_params(), net.output_scale
+    svc = {}
+    for side in sides:
+        big = nn.Net(side, side, 1, seed=seed)
+        big.set_params(p)
+        big.set_output_scale(scale)
+        svc[side] = S.SurrogateService(big, threshold=1e-2, judge_every=0)
+    reqs = [(sides[i % len(sides)], 40000 + seed + i) for i in range(n_req)]
+    lat_s, lat_p, outs = [], [], []
+    num = {k: 0.0 for k in ("band1", "band2", "band3", "band4", "residual", "all_bands")}
+    den = dict(num)
+    ident = []
+    for side, s in [(sides[0], 1), (sides[-1], 2)]:           # warm both sizes
+        fw = S.make_images(1, side, 50000 + s, spec=synth.megapixel_spec(side))
+        svc[side].decompose(torch.from_numpy(fw).to(dev))
+    for side, s in reqs:
+        f = torch.from_numpy(S.make_images(1, side, s, spec=synth.megapixel_spec(side))).to(dev)
+        r, t = S.timed(svc[side].decompose, f)
+        lat_s.append(t * 1e3)
+        ident.append(float(r["identity_error"][0]))
+        (pb, pr), tp = S.timed(S.decompose_dataset, f)
+        lat_p.append(tp * 1e3)
+        for j in range(4):
+            num["band%d" % (j + 1)] += float((r["bands"][0, j].double() - pb[0, j]).abs().sum())
+            den["band%d" % (j + 1)] += float(pb[0, j].abs().sum())
+        num["residual"] += float((r["residual"][0].double() - pr[0]).abs().sum())
+        den["residual"] += float(pr[0].abs().sum())
+        num["all_bands"] += float((r["bands"][0].double() - pb[0]).abs().sum())
+        den["all_bands"] += float(pb[0].abs().sum())
+        print("bench: megapixel request %dx%d surrogate %.1f ms plain %.1f ms" % (side, side, lat_s[-1], tp * 1e3),
+              file=sys.stderr, flush=True)
+    mpix = sum(side * side for side, _ in reqs) / 1e6
+    rec = {"workload": "3-channel shape images, 300 shapes, radius U[3,400], noise 0.02, sides %s alternating; "
+                       "one request at a time" % list(sides),
+           "requests": n_req,
+           "surrogate": {"MPix_per_s": mpix / (sum(lat_s) / 1e3), "p50_ms": percentile(lat_s, 50),
+                         "p99_ms": percentile(lat_s, 99),
+                         "fallbacks": sum(v.fallbacks for v in svc.values()), "threshold": 1e-2},
+           "plain": {"MPix_per_s": mpix / (sum(lat_p) / 1e3), "p50_ms": percentile(lat_p, 50),
+                     "p99_ms": percentile(lat_p, 99), "flow": dict(S.FLOW)},
+           "band_rel_l1": {k: num[k] / den[k] for k in num},
+           "identity_error": {"mean": float(np.mean(ident)), "max": float(np.max(ident))}}
+    rec["speedup"] = rec["surrogate"]["MPix_per_s"] / rec["plain"]["MPix_per_s"]
+    for v in svc.values():
+        v.net.close()
     return rec
 
 

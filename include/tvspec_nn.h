@@ -119,6 +119,16 @@ TVSPEC_API int tvspec_net_set_params(tvspec_net *net, const float *host, long lo
 TVSPEC_API int tvspec_net_set_output_scale(tvspec_net *net, const float *scale);
 
 /*
+ * Floor of the loss's denominators: each group's ||t_bj||^2 is raised by
+ * kappa 3 H W scale_j^2, kappa times the energy of a group whose RMS equals
+ * its output scale (the dataset's typical band size when the scales are set
+ * that way).  An image with a nearly empty band (a crop inside a large flat
+ * shape has almost no coarse-scale content) then cannot dominate a batch's
+ * gradient.  kappa = 0 (the default) is the paper's loss; kappa finite, >= 0.
+ */
+TVSPEC_API int tvspec_net_set_loss_floor(tvspec_net *net, float kappa);
+
+/*
  * Forward pass.  f device float32 [B][3][H][W]; out device float32
  * [B][15][H][W] (channel 3j + c = band j of colour c for j < 4, 12 + c =
  * residual of colour c, which is f + scale * the last layer's channel).
@@ -127,15 +137,27 @@ TVSPEC_API int tvspec_net_set_output_scale(tvspec_net *net, const float *scale);
 TVSPEC_API int tvspec_net_forward(tvspec_net *net, const float *f, int B, float *out, void *stream);
 
 /*
+ * Forward pass that also checks its result: as tvspec_net_forward, and
+ * err (device float32 [B], or NULL) receives each image's
+ * reconstruction-identity error as tvspec_net_identity_error defines it,
+ * computed on the stored outputs while they are written (no second pass
+ * over out; the sum runs in a fixed order, so the value is deterministic,
+ * and equals tvspec_net_identity_error's up to the order of summation).
+ */
+TVSPEC_API int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B, float *out, float *err,
+                                          void *stream);
+
+/*
  * One training step on a batch: forward, normalised MSE loss against the
  * decomposition (bands device float64 [B][4][3][H][W], residual device
  * float64 [B][3][H][W], the layouts of tvspec_decompose_batch_dev with four
  * bands), backward, one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8).
  * The loss groups the output into 5 bands of 3 channels (the 4 bands and
- * the residual):  (1/(5B)) sum_b sum_j ||o_bj - t_bj||^2 / ||t_bj||^2 with
+ * the residual):  (1/(5B)) sum_b sum_j ||o_bj - t_bj||^2 / (||t_bj||^2 + floor_j) with
  * t_bj the band for j < 4; for the residual group the numerator is
  * ||o - residual||^2 and the denominator ||residual - f||^2, the size of what
- * the residual's learned part has to carry.  A group with a zero
+ * the residual's learned part has to carry; floor_j is set by
+ * tvspec_net_set_loss_floor (0 by default).  A group with a zero
  * denominator contributes 0.
  * *loss (host) receives the batch loss; the call waits for the stream.
  */

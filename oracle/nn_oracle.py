@@ -109,9 +109,12 @@ def upsample2_grad(dy):
     return dy.reshape(B, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
 
 
-def nmse_loss(o, t, groups):
+def nmse_loss(o, t, groups, floor=None):
     """Normalised MSE (Sec. 3): o, t [B,H,W,G*g]; the output channels form
-    `groups` bands of equal width.  Returns (loss, d loss / d o)."""
+    `groups` bands of equal width.  Returns (loss, d loss / d o).
+
+    floor (optional, [groups]) is added to each band's squared norm in the
+    denominator (0 gives the paper's loss)."""
     B = o.shape[0]
     g = o.shape[3] // groups
     loss = 0.0
@@ -120,7 +123,7 @@ def nmse_loss(o, t, groups):
         for j in range(groups):
             sl = (b, slice(None), slice(None), slice(j * g, (j + 1) * g))
             num = np.sum((o[sl] - t[sl]) ** 2)
-            den = np.sum(t[sl] ** 2)
+            den = np.sum(t[sl] ** 2) + (0.0 if floor is None else floor[j])
             loss += num / den
             grad[sl] = 2.0 * (o[sl] - t[sl]) / den
     return loss / (B * groups), grad / (B * groups)

@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -541,17 +542,74 @@ __global__ __launch_bounds__(kT) void k_pack_target(const double *__restrict__ b
     }
 }
 
-// o [P][16] float -> out [B][15][H][W], the residual channels plus f [B][3][H][W].
-__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, const float *__restrict__ f,
-                                                      float *__restrict__ out, int B, long long HW)
+__device__ __forceinline__ double block_sum_d(double v, double *sh)
 {
-    const long long n = B * HW * kOutC;
-    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
-        const long long pix = q % HW;
-        const int c = (int)((q / HW) % kOutC);
-        const long long b = q / (HW * kOutC);
-        const float v = o[(size_t)(b * HW + pix) * kOutPad + c];
-        out[q] = c >= 3 * TVSPEC_NET_BANDS ? v + f[(b * 3 + c - 3 * TVSPEC_NET_BANDS) * HW + pix] : v;
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// o [P][16] float -> out [B][15][H][W], the residual channels plus f
+// [B][3][H][W].  One thread per pixel (its 16 values are one 64-byte row of
+// o).  With part != nullptr the block also writes part[b][blockIdx.x], the
+// sum over its pixels and the 3 channels of |f - sum_j band_j - residual|
+// taken on the stored outputs (the reconstruction identity, Eq. (7)).
+// Grid (blocks per image, B).
+__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, const float *__restrict__ f,
+                                                      float *__restrict__ out, long long HW,
+                                                      double *__restrict__ part)
+{
+    __shared__ double sh[kT / 64];
+    const int b = blockIdx.y;
+    double acc = 0.0;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < HW; q += (long long)gridDim.x * kT) {
+        const float4 *op = (const float4 *)(o + (size_t)(b * HW + q) * kOutPad);
+        float v[kOutPad];
+#pragma unroll
+        for (int k = 0; k < kOutPad / 4; ++k) {
+            const float4 t = op[k];
+            v[4 * k] = t.x;
+            v[4 * k + 1] = t.y;
+            v[4 * k + 2] = t.z;
+            v[4 * k + 3] = t.w;
+        }
+        float *ob = out + (size_t)b * kOutC * HW + q;
+#pragma unroll
+        for (int c = 0; c < 3 * TVSPEC_NET_BANDS; ++c)
+            ob[(size_t)c * HW] = v[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float fc = f[((size_t)b * 3 + c) * HW + q];
+            const float rc = v[3 * TVSPEC_NET_BANDS + c] + fc;
+            ob[(size_t)(3 * TVSPEC_NET_BANDS + c) * HW] = rc;
+            float d = fc;
+#pragma unroll
+            for (int j = 0; j < TVSPEC_NET_BANDS; ++j)
+                d -= v[3 * j + c];
+            d -= rc;
+            acc += fabsf(d);
+        }
+    }
+    if (part) {
+        const double t = block_sum_d(acc, sh);
+        if (threadIdx.x == 0)
+            part[(size_t)b * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// err[b] = (sum of part[b][0..nblk) in order) / (3 HW).
+__global__ __launch_bounds__(kT) void k_identity_total(const double *__restrict__ part, int B, int nblk, long long HW,
+                                                       float *__restrict__ err)
+{
+    for (int b = threadIdx.x; b < B; b += kT) {
+        double s = 0.0;
+        for (int k = 0; k < nblk; ++k)
+            s += part[(size_t)b * nblk + k];
+        err[b] = (float)(s / (3.0 * (double)HW));
     }
 }
 
@@ -600,16 +658,19 @@ __global__ __launch_bounds__(kT) void k_loss_partial(const float *__restrict__ o
     }
 }
 
-// nd[b][j][2] = totals (fixed order); loss[0] = (1/(5B)) sum num/den.  One
-// block: thread t totals the pairs t, t + 256, ...; the loss terms are then
-// added in a fixed order.
+// nd[b][j][2] = totals (fixed order), the denominator raised by the floor
+// kappa 3 HW scale_j^2 (the energy of a group whose RMS is its output
+// scale); loss[0] = (1/(5B)) sum num/den.  One block: thread t totals the
+// pairs t, t + 256, ...; the loss terms are then added in a fixed order.
 __global__ __launch_bounds__(kT) void k_loss_total(const float *__restrict__ part, int B, int nblk,
+                                                   const float *__restrict__ oscale, float kappa, long long HW,
                                                    float *__restrict__ nd, float *__restrict__ loss)
 {
     __shared__ double sl[kT];
     double l = 0.0;
     for (int bj = threadIdx.x; bj < B * kGroups; bj += kT) {
-        double a = 0.0, d = 0.0;
+        const double sj = oscale[3 * (bj % kGroups)];
+        double a = 0.0, d = (double)kappa * 3.0 * (double)HW * sj * sj;
         for (int k = 0; k < nblk; ++k) {
             a += part[((size_t)bj * nblk + k) * 2];
             d += part[((size_t)bj * nblk + k) * 2 + 1];
@@ -837,7 +898,15 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
 }
 
 std::mutex g_raw_mu;
-Work g_raw_work;
+std::map<int, Work> g_raw_work;  // per device
+
+int raw_work(Work **wk)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    *wk = &g_raw_work[dev];
+    return TVSPEC_OK;
+}
 
 // ---------------------------------------------------------------------------
 // the network
@@ -870,12 +939,14 @@ struct tvspec_net {
     long long nparams = 0;
     float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     long long step = 0;
+    float kappa = 0.f;        // loss denominator floor (0: the paper's loss)
     // activations: x0, e1a, e1b, p1, e2a, e2b, p2, e3a, e3b, p3, e4a, e4b, c3, d3a, d3b, c2, d2a, d2b, c1, d1a, d1b
     tvspec::nn::Act A[21];
     float *out = nullptr;     // [P][16]
     float *tgt = nullptr;     // [P][16]
     __bf16 *dout = nullptr;   // [P][16]
     float *lpart = nullptr, *nd = nullptr, *loss = nullptr;
+    double *ipart = nullptr;  // [max_batch][lblk] identity-error partials
     float *oscale = nullptr;  // [16] output channel scales (1 by default)
     int lblk = 0;
     tvspec::nn::Work wk;
@@ -977,7 +1048,8 @@ int loss_and_grad(tvspec_net *n, const float *f, const double *bands, const doub
     const long long HW = (long long)n->H * n->W;
     hipLaunchKernelGGL(k_pack_target, dim3(grid_for(B * HW)), dim3(kT), 0, st, bands, res, f, n->tgt, B, HW);
     hipLaunchKernelGGL(k_loss_partial, dim3(n->lblk, B), dim3(kT), 0, st, n->out, n->tgt, HW, n->lpart);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(kT), 0, st, n->lpart, B, n->lblk, n->nd, n->loss);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(kT), 0, st, n->lpart, B, n->lblk, n->oscale, n->kappa, HW, n->nd,
+                       n->loss);
     hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(B * HW * kOutPad)), dim3(kT), 0, st, n->out, n->tgt, n->nd,
                        n->oscale, B, HW, n->dout);
     HIP_TRY(hipGetLastError());
@@ -1080,7 +1152,9 @@ extern "C" int tvspec_nn_conv3x3_dgrad(const void *dy, int B, int H, int W, int 
         (long long)B * H * W > (1LL << 31))
         return fail(TVSPEC_EINVAL, "need B, H, W >= 1, Cout a multiple of 8, Cin a multiple of 16");
     std::lock_guard<std::mutex> lock(g_raw_mu);
-    return conv_dgrad(g_raw_work, (const __bf16 *)dy, B, H, W, Cout, (const __bf16 *)w, Cin, (const __bf16 *)mask,
+    Work *wk = nullptr;
+    TVSPEC_TRY(raw_work(&wk));
+    return conv_dgrad(*wk, (const __bf16 *)dy, B, H, W, Cout, (const __bf16 *)w, Cin, (const __bf16 *)mask,
                       (__bf16 *)dx, (hipStream_t)stream);
 }
 
@@ -1093,7 +1167,9 @@ extern "C" int tvspec_nn_conv3x3_wgrad(const void *x, const void *dy, int B, int
     if (B < 1 || H < 1 || W < 1 || Cin < 8 || Cin % 8 || Cout < 8 || Cout % 8 || (long long)B * H * W > (1LL << 31))
         return fail(TVSPEC_EINVAL, "need B, H, W >= 1, Cin and Cout multiples of 8");
     std::lock_guard<std::mutex> lock(g_raw_mu);
-    return conv_wgrad(g_raw_work, (const __bf16 *)x, (const __bf16 *)dy, B, H, W, Cin, Cout, dw, db,
+    Work *wk = nullptr;
+    TVSPEC_TRY(raw_work(&wk));
+    return conv_wgrad(*wk, (const __bf16 *)x, (const __bf16 *)dy, B, H, W, Cin, Cout, dw, db,
                       (hipStream_t)stream);
 }
 
@@ -1171,7 +1247,7 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
             return cleanup(rc);
     }
     const size_t P = (size_t)max_batch * H * W;
-    n->lblk = (int)std::min<long long>(256, ((long long)H * W + kT - 1) / kT);
+    n->lblk = (int)std::min<long long>(1024, ((long long)H * W + kT - 1) / kT);
     int rc = net_alloc(n, (void **)&n->out, P * kOutPad * sizeof(float));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->tgt, P * kOutPad * sizeof(float));
@@ -1181,6 +1257,8 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
         rc = net_alloc(n, (void **)&n->lpart, (size_t)max_batch * kGroups * n->lblk * 2 * sizeof(float));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->nd, (size_t)max_batch * kGroups * 2 * sizeof(float));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->ipart, (size_t)max_batch * n->lblk * sizeof(double));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->loss, sizeof(float));
     if (rc == TVSPEC_OK)
@@ -1272,7 +1350,20 @@ extern "C" int tvspec_net_set_output_scale(tvspec_net *net, const float *scale)
     return TVSPEC_OK;
 }
 
-extern "C" int tvspec_net_forward(tvspec_net *net, const float *f, int B, float *out, void *stream)
+extern "C" int tvspec_net_set_loss_floor(tvspec_net *net, float kappa)
+{
+    g_last_error.clear();
+    if (!net)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (!(kappa >= 0.f) || !std::isfinite(kappa))
+        return fail(TVSPEC_EINVAL, "kappa must be finite and >= 0");
+    std::lock_guard<std::mutex> lock(net->mu);
+    net->kappa = kappa;
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B, float *out, float *err,
+                                         void *stream)
 {
     g_last_error.clear();
     if (!net || !f || !out)
@@ -1282,9 +1373,17 @@ extern "C" int tvspec_net_forward(tvspec_net *net, const float *f, int B, float 
     hipStream_t st = (hipStream_t)stream;
     TVSPEC_TRY(forward(net, f, B, st));
     const long long HW = (long long)net->H * net->W;
-    hipLaunchKernelGGL(k_unpack_output, dim3(grid_for(B * HW * kOutC)), dim3(kT), 0, st, net->out, f, out, B, HW);
+    hipLaunchKernelGGL(k_unpack_output, dim3(net->lblk, B), dim3(kT), 0, st, net->out, f, out, HW,
+                       err ? net->ipart : nullptr);
+    if (err)
+        hipLaunchKernelGGL(k_identity_total, dim3(1), dim3(kT), 0, st, net->ipart, B, net->lblk, HW, err);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_forward(tvspec_net *net, const float *f, int B, float *out, void *stream)
+{
+    return tvspec_net_forward_checked(net, f, B, out, nullptr, stream);
 }
 
 extern "C" int tvspec_net_loss_grad(tvspec_net *net, const float *f, const double *bands, const double *residual,

@@ -23,7 +23,9 @@ EXPORTS = (
     "tvspec_net_get_params",
     "tvspec_net_set_params",
     "tvspec_net_set_output_scale",
+    "tvspec_net_set_loss_floor",
     "tvspec_net_forward",
+    "tvspec_net_forward_checked",
     "tvspec_net_train_step",
     "tvspec_net_loss_grad",
     "tvspec_net_identity_error",
@@ -55,8 +57,12 @@ _lib.tvspec_net_set_params.argtypes = [_vp, _vp, _ll]
 _lib.tvspec_net_set_params.restype = _i
 _lib.tvspec_net_set_output_scale.argtypes = [_vp, _vp]
 _lib.tvspec_net_set_output_scale.restype = _i
+_lib.tvspec_net_set_loss_floor.argtypes = [_vp, _f]
+_lib.tvspec_net_set_loss_floor.restype = _i
 _lib.tvspec_net_forward.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.tvspec_net_forward.restype = _i
+_lib.tvspec_net_forward_checked.argtypes = [_vp, _vp, _i, _vp, _vp, _vp]
+_lib.tvspec_net_forward_checked.restype = _i
 _lib.tvspec_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i, _f, ctypes.POINTER(_f), _vp]
 _lib.tvspec_net_train_step.restype = _i
 _lib.tvspec_net_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_f), _vp, _vp]
@@ -150,8 +156,17 @@ def tvspec_net_set_output_scale(h, scale):
     _check(_lib.tvspec_net_set_output_scale(h, s.ctypes.data))
 
 
+def tvspec_net_set_loss_floor(h, kappa):
+    _check(_lib.tvspec_net_set_loss_floor(h, float(kappa)))
+
+
 def tvspec_net_forward(h, f, out, stream=None):
     _check(_lib.tvspec_net_forward(h, f.data_ptr(), f.shape[0], out.data_ptr(), _stream(f, stream)))
+
+
+def tvspec_net_forward_checked(h, f, out, err, stream=None):
+    _check(_lib.tvspec_net_forward_checked(h, f.data_ptr(), f.shape[0], out.data_ptr(),
+                                           err.data_ptr() if err is not None else None, _stream(f, stream)))
 
 
 def tvspec_net_train_step(h, f, bands, residual, lr, stream=None):
@@ -228,13 +243,23 @@ class Net:
         tvspec_net_set_output_scale(self._h, scale)
         self.output_scale = np.asarray(scale, dtype=np.float32)
 
-    def forward(self, f, out=None, stream=None):
-        """f [B,3,H,W] float32 -> [B,15,H,W] float32 (4 bands x 3, residual x 3)."""
+    def set_loss_floor(self, kappa):
+        """Floor of the loss's denominators (see the header); 0 = the paper's loss."""
+        tvspec_net_set_loss_floor(self._h, kappa)
+
+    def forward(self, f, out=None, stream=None, identity=False):
+        """f [B,3,H,W] float32 -> [B,15,H,W] float32 (4 bands x 3, residual x 3);
+        with identity=True also each image's reconstruction-identity error
+        [B] (float32, on the device), computed while the output is written."""
         self._check_f(f)
         if out is None:
             out = torch.empty((f.shape[0], OUT_CHANNELS, self.H, self.W), dtype=torch.float32, device=f.device)
-        tvspec_net_forward(self._h, f, out, stream)
-        return out
+        if not identity:
+            tvspec_net_forward(self._h, f, out, stream)
+            return out
+        err = torch.empty((f.shape[0],), dtype=torch.float32, device=f.device)
+        tvspec_net_forward_checked(self._h, f, out, err, stream)
+        return out, err
 
     def train_step(self, f, bands, residual, lr, stream=None):
         self._check_f(f)

@@ -5,6 +5,8 @@ Sec. 3 of the paper trains a network on decompositions the model-driven
 method computes (its ground truth) and Sec. 4.3 compares their cost.  Here:
 
   make_images        seeded synthetic 3-channel shape images (synth.py)
+  make_training_images  the training mix: serving-spec images and crops of
+                     megapixel-spec images
   decompose_dataset  their decompositions by the batched GPU path
                      (tvspec_decompose_batch_dev) with the flow FLOW
   train              Adam steps of tvspec_net_train_step on random minibatches
@@ -28,16 +30,21 @@ import numpy as np
 import torch
 
 from . import synth, tvspec
-from .nn import BANDS, IN_CHANNELS, OUT_CHANNELS, Net, tvspec_net_identity_error
+from .nn import BANDS, IN_CHANNELS, OUT_CHANNELS, Net
 
 # The decomposition the network learns: dt 0.005, K 100 samples, 150 inner
 # iterations per ROF solve, 4 dyadic bands {0, 1, 2, 4, 100} and the residual.
 FLOW = dict(dt=0.005, K=100, iters=150, edges=[0, 1, 2, 4, 100])
 
+# Floor of the training loss's denominators (tvspec_net_set_loss_floor): 5%
+# of the energy of a band at the dataset's RMS size.
+LOSS_FLOOR = 0.05
 
-def make_images(n, side, seed0, threads=16):
-    """n seeded images [n, 3, side, side] float32 (synth.serving_spec)."""
-    spec = synth.serving_spec(side)
+
+def make_images(n, side, seed0, threads=16, spec=None):
+    """n seeded images [n, 3, side, side] float32 (spec, by default
+    synth.serving_spec(side))."""
+    spec = spec or synth.serving_spec(side)
     out = np.empty((n, IN_CHANNELS, side, side), np.float32)
 
     def work(i):
@@ -46,6 +53,24 @@ def make_images(n, side, seed0, threads=16):
     with ThreadPoolExecutor(threads) as ex:
         list(ex.map(work, range(n)))
     return out
+
+
+def make_training_images(n, side, seed0, threads=16, crop_from=4):
+    """The surrogate's training mix, n images [n, 3, side, side] float32: the
+    first half drawn with synth.serving_spec(side), the rest side x side
+    crops (a crop_from x crop_from grid of tiles) of images drawn with
+    synth.megapixel_spec(crop_from * side), so that the network also sees
+    the local statistics of megapixel images (their noise level, dense
+    and large shapes)."""
+    n_a = (n + 1) // 2
+    a = make_images(n_a, side, seed0, threads)
+    per = crop_from * crop_from
+    n_big = (n - n_a + per - 1) // per
+    big = make_images(n_big, crop_from * side, seed0 + 1000003, threads,
+                      spec=synth.megapixel_spec(crop_from * side))
+    tiles = big.reshape(n_big, IN_CHANNELS, crop_from, side, crop_from, side).transpose(0, 2, 4, 1, 3, 5)
+    tiles = tiles.reshape(n_big * per, IN_CHANNELS, side, side)[:n - n_a]
+    return np.ascontiguousarray(np.concatenate([a, tiles]))
 
 
 def decompose_dataset(f, flow=FLOW, chunk=64, precision="mixed"):
@@ -139,8 +164,8 @@ class SurrogateService:
     def decompose(self, f):
         """f [B, 3, H, W] float32 -> dict(bands [B,4,3,H,W], residual [B,3,H,W]
         float32, source ['surrogate' | 'plain'] per image, identity_error)."""
-        out = self.net.forward(f)
-        err = tvspec_net_identity_error(f, out).cpu().numpy()
+        out, err = self.net.forward(f, identity=True)
+        err = err.cpu().numpy()
         bands, res = split_output(out)
         bands, res = bands.clone(), res.clone()
         src = ["surrogate"] * f.shape[0]

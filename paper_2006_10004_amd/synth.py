@@ -63,23 +63,33 @@ def shapes_image(spec: ShapeSpec, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     H, W, C = spec.H, spec.W, spec.C
     img = np.full((C, H, W), spec.background, dtype=np.float64)
-    ii = np.arange(H, dtype=np.float64)[:, None]
-    jj = np.arange(W, dtype=np.float64)[None, :]
     for _ in range(spec.n_shapes):
         kind = spec.kinds[int(rng.integers(len(spec.kinds)))]
         cy = rng.uniform(0, H)
         cx = rng.uniform(0, W)
         if kind == DISK:
             r = rng.uniform(spec.size_lo, spec.size_hi)
-            mask = (ii - cy) ** 2 + (jj - cx) ** 2 <= r * r
+            ext = (r, r)
         elif kind == RECT:
             hy = rng.uniform(spec.size_lo, spec.size_hi)
             hx = rng.uniform(spec.size_lo, spec.size_hi)
-            mask = (np.abs(ii - cy) <= hy) & (np.abs(jj - cx) <= hx)
+            ext = (hy, hx)
         else:
             a = rng.uniform(spec.size_lo, spec.size_hi)
             b = rng.uniform(spec.size_lo, spec.size_hi)
             th = rng.uniform(0, np.pi)
+            ext = (max(a, b), max(a, b))
+        # the shape lies within its half-extents of the centre: evaluate its
+        # mask on that box (with a 2-pixel margin) only
+        i0, i1 = max(0, int(np.floor(cy - ext[0])) - 2), min(H, int(np.ceil(cy + ext[0])) + 3)
+        j0, j1 = max(0, int(np.floor(cx - ext[1])) - 2), min(W, int(np.ceil(cx + ext[1])) + 3)
+        ii = np.arange(i0, i1, dtype=np.float64)[:, None]
+        jj = np.arange(j0, j1, dtype=np.float64)[None, :]
+        if kind == DISK:
+            mask = (ii - cy) ** 2 + (jj - cx) ** 2 <= r * r
+        elif kind == RECT:
+            mask = (np.abs(ii - cy) <= hy) & (np.abs(jj - cx) <= hx)
+        else:
             ct, st = np.cos(th), np.sin(th)
             y = ii - cy
             x = jj - cx
@@ -88,7 +98,7 @@ def shapes_image(spec: ShapeSpec, seed: int) -> np.ndarray:
             mask = (xr / a) ** 2 + (yr / b) ** 2 <= 1.0
         contrasts = rng.uniform(-spec.contrast, spec.contrast, size=C)
         for c in range(C):
-            img[c][mask] = spec.background + contrasts[c]
+            img[c, i0:i1, j0:j1][mask] = spec.background + contrasts[c]
     if spec.sigma > 0:
         img += rng.normal(0.0, spec.sigma, size=img.shape)
     np.clip(img, 0.0, 1.0, out=img)

@@ -166,8 +166,12 @@ def test_network_forward_against_oracle(nn, small_net):
     assert rel(o[:, 12:] - f, ref[:, 12:] - f) < 1e-2
 
 
-def test_network_loss_and_gradients_against_oracle(nn, small_net):
+@pytest.mark.parametrize("kappa", [0.0, 0.01])
+def test_network_loss_and_gradients_against_oracle(nn, small_net, kappa):
+    """kappa: the loss's denominator floor, kappa 3 H W scale_j^2 with the
+    default output scales of 1."""
     net, p = small_net
+    net.set_loss_floor(kappa)
     f, bands, res = inputs(2)
     loss, g = net.loss_grad(torch.from_numpy(f).to(DEV), torch.from_numpy(bands).to(DEV),
                             torch.from_numpy(res).to(DEV))
@@ -176,7 +180,8 @@ def test_network_loss_and_gradients_against_oracle(nn, small_net):
     params = oracle_params(p, nn)
     y, cache = model.forward(params, x)
     t = to_f32_np(orc_nn.surrogate_target(f, bands, res))
-    ref_loss, dy = orc_nn.nmse_loss(y, t, 5)
+    ref_loss, dy = orc_nn.nmse_loss(y, t, 5, floor=np.full(5, kappa * 3 * 32 * 32))
+    net.set_loss_floor(0.0)
     assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
     scales = {}
     ref_g = model.backward(params, cache, to_bf16_np(dy), scales=scales)

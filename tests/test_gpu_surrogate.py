@@ -54,6 +54,27 @@ def test_identity_error_against_oracle(mods, B, H, W):
     assert np.allclose(err, ref, rtol=1e-5, atol=1e-7), (err, ref)
 
 
+@pytest.mark.parametrize("H,W,B", [(8, 8, 1), (24, 40, 3), (256, 256, 2)])
+def test_forward_checked_identity_error(mods, H, W, B):
+    """The identity error computed while the output is written equals the
+    oracle's on the stored output (up to the order of summation), and the
+    output is the plain forward pass's, bit for bit."""
+    nn = mods[0]
+    net = nn.Net(H, W, 4, seed=7)
+    p = net.get_params()
+    net.set_params(p + 1e-3 * np.random.default_rng(8).standard_normal(p.size).astype(np.float32))
+    net.set_output_scale(np.linspace(0.01, 0.1, 15).astype(np.float32))
+    f = torch.from_numpy(np.random.default_rng(9).random((B, 3, H, W)).astype(np.float32)).to(DEV)
+    out, err = net.forward(f, identity=True)
+    plain = net.forward(f)
+    assert torch.equal(out, plain)
+    ref = orc_nn.identity_error(f.cpu().numpy(), out.cpu().numpy())
+    assert np.allclose(err.cpu().numpy(), ref, rtol=1e-5, atol=0), (err, ref)
+    alone = nn.tvspec_net_identity_error(f, out).cpu().numpy()
+    assert np.allclose(err.cpu().numpy(), alone, rtol=1e-5, atol=0)
+    net.close()
+
+
 def perturbed(nn, scale, seed):
     net = nn.Net(64, 64, 4, seed=seed)
     p = net.get_params()

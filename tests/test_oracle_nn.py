@@ -87,6 +87,27 @@ def test_nmse_loss_closed_forms_and_gradient():
         assert abs(fd - g[idx]) < 1e-6
 
 
+def test_nmse_loss_floor():
+    """With a floor F_j in the denominators: o = 0 gives the mean of
+    ||t_bj||^2 / (||t_bj||^2 + F_j); a zero floor is the plain loss; the
+    gradient still matches finite differences."""
+    t = RNG.standard_normal((2, 4, 5, 6))
+    F = np.array([0.5, 3.0, 20.0])
+    loss, _ = nn.nmse_loss(np.zeros_like(t), t, 3, floor=F)
+    e = [np.sum(t[b, :, :, 2 * j:2 * j + 2] ** 2) for b in range(2) for j in range(3)]
+    want = np.mean([e[3 * b + j] / (e[3 * b + j] + F[j]) for b in range(2) for j in range(3)])
+    assert abs(loss - want) < 1e-15
+    o = RNG.standard_normal(t.shape)
+    assert nn.nmse_loss(o, t, 3, floor=np.zeros(3))[0] == nn.nmse_loss(o, t, 3)[0]
+    loss, g = nn.nmse_loss(o, t, 3, floor=F)
+    h = 1e-7
+    for idx in [(0, 0, 0, 0), (1, 3, 4, 5)]:
+        d = np.zeros_like(o)
+        d[idx] = h
+        fd = (nn.nmse_loss(o + d, t, 3, floor=F)[0] - nn.nmse_loss(o - d, t, 3, floor=F)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-6
+
+
 def test_adam_closed_forms():
     # with a constant gradient the bias-corrected moments are g and g^2, so
     # every step moves each weight by lr g / (|g| + eps)
