@@ -238,6 +238,38 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     return rec
 
 
+def surrogate_forward_only(reps, batch=16, side=256, seed=11):
+    """Forward passes of a freshly initialised network on one batch of
+    `batch` 3 x side^2 shape images (dense convolutions cost the same for
+    any weight values): the network's inference throughput and MFMA
+    roofline alone, without training; the command to profile its kernels."""
+    import torch
+    from paper_2006_10004_amd import nn, surrogate as S
+
+    dev = torch.device("cuda:0")
+    net = nn.Net(side, side, batch, seed=seed)
+    x = torch.from_numpy(S.make_images(batch, side, 70000 + seed)).to(dev)
+    out = net.forward(x)
+    for _ in range(3):
+        net.forward(x, out)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(x, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = S.conv_flops(side, side) * batch
+    achieved = flops / (ms / 1e3) / 1e12
+    net.close()
+    return {"workload": "network forward, batch %d of 3x%dx%d" % (batch, side, side), "reps": reps, "ms": ms,
+            "MPix_per_s": batch * side * side / 1e6 / (ms / 1e3),
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "flops_per_pass": flops}}
+
+
 def megapixel_serving(net, sides, n_req, seed):
     """Megapixel requests served one at a time (each waited for): through the
     surrogate service (identity-error fallback at 1e-2) and through the plain
@@ -425,9 +457,12 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--pdhg-steps", type=int, default=3,
                     help="also time this many decompositions with the primal-dual solver (0 = skip)")
-    ap.add_argument("--sur-train-images", type=int, default=1024,
+    ap.add_argument("--sur-train-images", type=int, default=2048,
                     help="training images of the learned surrogate (0 = skip the surrogate)")
-    ap.add_argument("--sur-steps", type=int, default=1500, help="Adam steps of the surrogate's training")
+    ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the surrogate's training")
+    ap.add_argument("--sur-forward-only", type=int, default=0, metavar="N",
+                    help="instead of the benchmark, time N forward passes of the surrogate network "
+                         "(batch 16 of 3x256x256) and print that record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -453,6 +488,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
                           "dispatches": 4}), flush=True)
+        return
+
+    if args.sur_forward_only > 0:
+        print(json.dumps(surrogate_forward_only(args.sur_forward_only)), flush=True)
         return
 
     from paper_2006_10004_amd import synth, tvspec
