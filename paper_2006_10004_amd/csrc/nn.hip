@@ -61,95 +61,138 @@ __device__ __forceinline__ bf16x8 zero8()
 // ---------------------------------------------------------------------------
 // convolution (forward and input gradient)
 
-// Y[p][o] = epilogue(sum_k A[p][k] Wt[o][k]), Wt [Cout][9][Cin].
-// Epilogue: + bias[o] (bias != nullptr), max(., 0) (relu), zero where
-// mask[p][o] <= 0 (mask != nullptr), times oscale[o] (oscale != nullptr);
-// stored as bf16 or f32.
+// Y[p][o] = epilogue(sum_{tap, c} X[p + tap offset][c] Wt[o][tap][c]),
+// Wt [Cout][9][Cin].  Epilogue: + bias[o] (bias != nullptr), max(., 0)
+// (relu), zero where mask[p][o] <= 0 (mask != nullptr), times oscale[o]
+// (oscale != nullptr); stored as bf16 or f32.
 //
-// A workgroup (4 waves) covers 256 pixels x NF*16 output channels; each
-// wave 64 pixels (4 row fragments) x NF column fragments, 4 NF MFMAs per
-// step of 32 values of k.  The weight tile of a step (NF*16 channels x 32 k)
-// is shared by the 4 waves through LDS, double-buffered (one barrier per
-// step); each wave's activation fragments are its own and come straight
-// from global memory, loaded one step ahead.
-constexpr int kConvPix = 256;  // pixels per workgroup
-constexpr int kBPitch = 40;    // LDS row pitch of the weight tile (32 k + 8)
+// Implicit GEMM over output pixels x output channels x (9 taps x Cin).  A
+// workgroup of WAVES waves owns a (2 WAVES) x 32 tile of output pixels of
+// one image and 16 NF output channels.  The input channels are taken in
+// chunks of CC: the chunk's (2 WAVES + 2) x (32 + 2) input pixels are
+// staged in LDS once, and all 9 taps read their operands from there (each
+// input value leaves HBM/L2 1.2 to 1.3 times instead of 9).  A chunk's
+// 9 CC values of k, tap-major (k = tap CC + c), make ceil(9 CC / 32) steps
+// of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) is
+// double-buffered in LDS, loaded one step ahead.  Wave w computes output
+// rows 2w, 2w + 1 (four 16-pixel row fragments) x NF column fragments of
+// v_mfma_f32_16x16x32_bf16.  Measured variants that hold more in flight
+// (8-wave workgroups, 64-wide k stages, weights two steps ahead, operand
+// fragments read a step ahead) were all slower: each costs registers or
+// LDS, and the lost occupancy outweighs the latency they hide.
+//
+// LDS pixel pitch: CC bf16 padded to an odd multiple of 16 bytes, so the
+// 16-byte operand reads of 8 (or 16) consecutive lanes, at consecutive
+// pixels, fall in distinct banks.
+constexpr int kTileX = 32;
+constexpr int kHaloX = kTileX + 2;
+constexpr int kBPitch = 40;  // LDS row pitch of the weight tile (32 k + 8; 20 dwords: 4 x odd)
 
-template <bool F32OUT, int NF>
-__global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
-                                                const float *__restrict__ bias, const __bf16 *__restrict__ mask,
-                                                const float *__restrict__ oscale, void *__restrict__ Y, int B,
-                                                int H, int W, int Cin, int Cout, int relu)
+template <int CC, int WAVES>
+struct ConvShape {
+    static_assert(CC % 8 == 0 && CC <= 64, "chunk of 8..64 channels");
+    static constexpr int kThreads = 64 * WAVES;
+    static constexpr int kTileY = 2 * WAVES;
+    static constexpr int kHaloPix = (kTileY + 2) * kHaloX;
+    static constexpr int kPitch = ((CC / 8) % 2 == 1) ? CC : CC + 8;  // bf16 per pixel in LDS
+    static constexpr int kSteps = (9 * CC + 31) / 32;
+    static constexpr int kGroups = CC / 8;                              // 16-byte groups per pixel
+    static constexpr int kItems = kHaloPix * kGroups;                   // 16-byte loads per chunk
+    static constexpr int kItemsPerThread = (kItems + kThreads - 1) / kThreads;
+};
+
+template <bool F32OUT, int NF, int CC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
+                                                        const float *__restrict__ bias,
+                                                        const __bf16 *__restrict__ mask,
+                                                        const float *__restrict__ oscale, void *__restrict__ Y, int B,
+                                                        int H, int W, int Cin, int Cout, int relu, int tiles_x,
+                                                        int tiles_y)
 {
+    using CS = ConvShape<CC, WAVES>;
+    constexpr int kPitch = CS::kPitch;
+    constexpr int kSteps = CS::kSteps;
+    constexpr int kNT = CS::kThreads;
+    __shared__ __attribute__((aligned(16))) __bf16 sX[CS::kHaloPix * kPitch];
     __shared__ __attribute__((aligned(16))) __bf16 sB[2][NF * 16 * kBPitch];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
-    const long long P = (long long)B * H * W;
-    const long long p0 = (long long)blockIdx.x * kConvPix + wave * 64;
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x;
+    const int ty = (tile / tiles_x) % tiles_y;
+    const int b = tile / (tiles_x * tiles_y);
+    const int y0 = ty * CS::kTileY;
+    const int x0 = tx * kTileX;
     const int co0 = blockIdx.y * (NF * 16);
     const int K = 9 * Cin;
-    const int nks = (K + 31) / 32;
+    const int nchunks = Cin / CC;
 
-    int pb[4], py[4], px[4];
-    bool pv[4];
+    // input staging: item i = (halo pixel i / kGroups, 16-byte group i % kGroups)
+    auto load_x = [&](int q, bf16x8 *v) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const long long p = p0 + r * 16 + r16;
-        pv[r] = p < P;
-        const long long q = pv[r] ? p : 0;
-        pb[r] = (int)(q / ((long long)H * W));
-        const int rem = (int)(q - (long long)pb[r] * H * W);
-        py[r] = rem / W;
-        px[r] = rem - py[r] * W;
-    }
-
-    // weight-tile staging: chunk c = t + 256 i is row c / 4 (output channel
-    // co0 + c / 4), 8 values of k at (c % 4) * 8 of the step
-    constexpr int kChunks = NF * 16 * 4;
-    constexpr int kCPT = (kChunks + kT - 1) / kT;
-    auto load_b = [&](int ks, bf16x8 *v) {
-#pragma unroll
-        for (int i = 0; i < kCPT; ++i) {
-            const int c = threadIdx.x + i * kT;
-            v[i] = zero8();
-            if (c < kChunks) {
-                const int co = co0 + (c >> 2);
-                const int k = ks * 32 + (c & 3) * 8;
-                if (co < Cout && k < K)
-                    v[i] = *(const bf16x8 *)(Wt + (size_t)co * K + k);
+        for (int j = 0; j < CS::kItemsPerThread; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            v[j] = zero8();
+            if (i < CS::kItems) {
+                const int hp = i / CS::kGroups;
+                const int cg = i - hp * CS::kGroups;
+                const int hy = hp / kHaloX;
+                const int hx = hp - hy * kHaloX;
+                const int yy = y0 + hy - 1;
+                const int xx = x0 + hx - 1;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v[j] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + q * CC + 8 * cg);
             }
         }
     };
-    auto store_b = [&](int buf, const bf16x8 *v) {
+    auto store_x = [&](const bf16x8 *v) {
 #pragma unroll
-        for (int i = 0; i < kCPT; ++i) {
-            const int c = threadIdx.x + i * kT;
-            if (c < kChunks)
+        for (int j = 0; j < CS::kItemsPerThread; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            if (i < CS::kItems) {
+                const int hp = i / CS::kGroups;
+                const int cg = i - hp * CS::kGroups;
+                *(bf16x8 *)(&sX[hp * kPitch + 8 * cg]) = v[j];
+            }
+        }
+    };
+    // weight staging for step s of chunk q: chunk c = t + kNT i is row c / 4
+    // (output channel co0 + c / 4), 8 values of k at (c % 4) * 8 of the step
+    constexpr int kWChunks = NF * 16 * 4;
+    constexpr int kWPT = (kWChunks + kNT - 1) / kNT;
+    auto load_w = [&](int q, int s, bf16x8 *v) {
+#pragma unroll
+        for (int i = 0; i < kWPT; ++i) {
+            const int c = threadIdx.x + i * kNT;
+            v[i] = zero8();
+            if (c < kWChunks) {
+                const int co = co0 + (c >> 2);
+                const int kc = s * 32 + (c & 3) * 8;  // k within the chunk
+                if (co < Cout && kc < 9 * CC) {
+                    const int tap = kc / CC;
+                    const int ch = kc - tap * CC;
+                    v[i] = *(const bf16x8 *)(Wt + (size_t)co * K + tap * Cin + q * CC + ch);
+                }
+            }
+        }
+    };
+    auto store_w = [&](int buf, const bf16x8 *v) {
+#pragma unroll
+        for (int i = 0; i < kWPT; ++i) {
+            const int c = threadIdx.x + i * kNT;
+            if (c < kWChunks)
                 *(bf16x8 *)(&sB[buf][(c >> 2) * kBPitch + (c & 3) * 8]) = v[i];
         }
     };
-    // this lane's activation fragments of step ks (k = 32 ks + 8 g)
-    auto load_a = [&](int ks, bf16x8 *a) {
-        const int k = ks * 32 + 8 * g;
+
+    // this lane's row fragments: output row lr = 2 wave + (r >> 1), columns
+    // 16 (r & 1) + r16; halo pixel of tap (0, 0)
+    int hbase[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            a[r] = zero8();
-        if (k < K) {
-            const int tap = k / Cin;
-            const int ch = k - tap * Cin;
-            const int dy = tap / 3 - 1;
-            const int dx = tap - (tap / 3) * 3 - 1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int yy = py[r] + dy;
-                const int xx = px[r] + dx;
-                if (pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    a[r] = *(const bf16x8 *)(X + ((size_t)((size_t)pb[r] * H + yy) * W + xx) * Cin + ch);
-            }
-        }
-    };
+    for (int r = 0; r < 4; ++r)
+        hbase[r] = (2 * wave + (r >> 1)) * kHaloX + 16 * (r & 1) + r16;
 
     floatx4 acc[4][NF];
 #pragma unroll
@@ -158,32 +201,51 @@ __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, co
         for (int c = 0; c < NF; ++c)
             acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    bf16x8 vb[kCPT], a[4], an[4];
-    load_b(0, vb);
-    store_b(0, vb);
-    load_a(0, a);
+    bf16x8 vx[CS::kItemsPerThread];
+    bf16x8 vw[kWPT];
+    load_x(0, vx);
+    store_x(vx);
+    load_w(0, 0, vw);
+    store_w(0, vw);
     __syncthreads();
-    for (int ks = 0; ks < nks; ++ks) {
-        const int cur = ks & 1;
-        const bool more = ks + 1 < nks;
-        if (more) {
-            load_b(ks + 1, vb);
-            load_a(ks + 1, an);
-        }
+    int buf = 0;
+    for (int q = 0; q < nchunks; ++q) {
+        const bool next_chunk = q + 1 < nchunks;
+        if (next_chunk)
+            load_x(q + 1, vx);
 #pragma unroll
-        for (int c = 0; c < NF; ++c) {
-            const bf16x8 bfr = *(const bf16x8 *)(&sB[cur][(c * 16 + r16) * kBPitch + 8 * g]);
+        for (int s = 0; s < kSteps; ++s) {
+            const bool last = s + 1 == kSteps;
+            const bool more = !last || next_chunk;
+            if (more)
+                load_w(last ? q + 1 : q, last ? 0 : s + 1, vw);
+            // operands of step s: k = 32 s + 8 g within the chunk
+            const int kc = s * 32 + 8 * g;
+            const bool kv = kc < 9 * CC;
+            const int tap = kv ? kc / CC : 0;
+            const int ch = kc - tap * CC;
+            const int off = ((tap / 3) * kHaloX + (tap - (tap / 3) * 3)) * kPitch + ch;
+            bf16x8 a[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
-        }
-        if (more) {
-            store_b(cur ^ 1, vb);
+                a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                a[r] = an[r];
+            for (int c = 0; c < NF; ++c) {
+                const bf16x8 bfr = *(const bf16x8 *)(&sB[buf][(c * 16 + r16) * kBPitch + 8 * g]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
+            }
+            if (more)
+                store_w(buf ^ 1, vw);
+            __syncthreads();
+            buf ^= 1;
         }
-        __syncthreads();
+        if (next_chunk) {
+            // every wave has read this chunk's tile (barrier above)
+            store_x(vx);
+            __syncthreads();
+        }
     }
 
 #pragma unroll
@@ -195,22 +257,24 @@ __global__ __launch_bounds__(kT) void k_conv3x3(const __bf16 *__restrict__ X, co
         const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            const int yy = y0 + 2 * wave + (r >> 1);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const long long p = p0 + r * 16 + 4 * g + i;
-                if (p >= P)
+                const int xx = x0 + 16 * (r & 1) + 4 * g + i;
+                if (yy >= H || xx >= W)
                     continue;
+                const size_t p = ((size_t)b * H + yy) * W + xx;
                 float v = acc[r][c][i] + bv;
                 if (relu)
                     v = v > 0.f ? v : 0.f;
-                if (mask && !((float)mask[(size_t)p * Cout + co] > 0.f))
+                if (mask && !((float)mask[p * Cout + co] > 0.f))
                     v = 0.f;
                 if (oscale)
                     v *= sv;
                 if constexpr (F32OUT)
-                    ((float *)Y)[(size_t)p * Cout + co] = v;
+                    ((float *)Y)[p * Cout + co] = v;
                 else
-                    ((__bf16 *)Y)[(size_t)p * Cout + co] = (__bf16)v;
+                    ((__bf16 *)Y)[p * Cout + co] = (__bf16)v;
             }
         }
     }
@@ -288,39 +352,52 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
     const int dy = tap / 3 - 1;
     const int dx = tap - (tap / 3) * 3 - 1;
 
-    for (int chunk = 0; chunk < cps; ++chunk) {
-        const long long pbase = ((long long)s * cps + chunk) * kWChunk;
-        if (pbase >= P)
-            break;
+    // the chunk's global loads go to registers one chunk ahead
+    bf16x8 va[2], vb[4];
+    auto load_chunk = [&](long long pbase) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int pl = spa + 32 * h;
-            const long long p = pbase + pl;
-            bf16x8 va = zero8();
+            const long long p = pbase + spa + 32 * h;
+            va[h] = zero8();
             if (p < P && oval)
-                va = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                sA[(sga * 8 + j) * kWPitch + swz(sga * 8 + j, pl)] = va[j];
+                va[h] = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
         }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            const int pl = spb + 16 * h;
-            const long long p = pbase + pl;
-            bf16x8 vb = zero8();
+            const long long p = pbase + spb + 16 * h;
+            vb[h] = zero8();
             if (p < P && kval) {
                 const int b = (int)(p / HW);
                 const int rem = (int)(p - (long long)b * HW);
                 const int yy = rem / W + dy;
                 const int xx = rem - (rem / W) * W + dx;
                 if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    vb = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
+                    vb[h] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
             }
+        }
+    };
+    const long long pfirst = (long long)s * cps * kWChunk;
+    const int nchunk = (int)min((long long)cps, (P - pfirst + kWChunk - 1) / kWChunk);
+    if (nchunk > 0)
+        load_chunk(pfirst);
+    for (int chunk = 0; chunk < nchunk; ++chunk) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int pl = spa + 32 * h;
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                sB[(sgb * 8 + j) * kWPitch + swz(sgb * 8 + j, pl)] = vb[j];
+                sA[(sga * 8 + j) * kWPitch + swz(sga * 8 + j, pl)] = va[h][j];
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int pl = spb + 16 * h;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                sB[(sgb * 8 + j) * kWPitch + swz(sgb * 8 + j, pl)] = vb[h][j];
         }
         __syncthreads();
+        if (chunk + 1 < nchunk)
+            load_chunk(pfirst + (long long)(chunk + 1) * kWChunk);
         if (do_bias && threadIdx.x < 64) {
 #pragma unroll
             for (int q = 0; q < kWChunk; q += 8) {
@@ -360,15 +437,53 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
         bpart[(size_t)s * Cout + o0 + threadIdx.x] = bacc;
 }
 
-// out[q] = sum_s part[s * n + q], s = 0 .. ns-1 in order.
-__global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ part, int ns, size_t n,
+// Fixed-order sum of the rows of part [ns][n] (n a multiple of 4, part
+// 16-byte aligned), in two stages so that narrow, tall partial arrays still
+// fill the device:
+//   stage 1 (k_reduce_groups): row g kRowGroup of part <- the sum of rows
+//   g kRowGroup .. g kRowGroup + kRowGroup - 1 in order (in place; blockIdx.y
+//   is the group g; each thread owns 4 consecutive columns);
+//   stage 2 (k_reduce_rows): out[q] = sum over groups g in order of row
+//   g kRowGroup (with one group, stage 1 is skipped and this is the plain
+//   sum over rows).
+constexpr int kRowGroup = 16;
+
+__global__ __launch_bounds__(kT) void k_reduce_groups(float *__restrict__ part, int ns, size_t n)
+{
+    const int g = blockIdx.y;
+    const int s0 = g * kRowGroup;
+    const int s1 = min(ns, s0 + kRowGroup);
+    const size_t n4 = n / 4;
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n4; q += (size_t)gridDim.x * kT) {
+        float4 a = ((const float4 *)(part + (size_t)s0 * n))[q];
+        for (int s = s0 + 1; s < s1; ++s) {
+            const float4 v = ((const float4 *)(part + (size_t)s * n))[q];
+            a.x += v.x;
+            a.y += v.y;
+            a.z += v.z;
+            a.w += v.w;
+        }
+        ((float4 *)(part + (size_t)s0 * n))[q] = a;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ part, int ns, int stride, size_t n,
                                                     float *__restrict__ out)
 {
-    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n; q += (size_t)gridDim.x * kT) {
-        float a = 0.f;
-        for (int s = 0; s < ns; ++s)
-            a += part[(size_t)s * n + q];
-        out[q] = a;
+    const size_t n4 = n / 4;
+    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n4; q += (size_t)gridDim.x * kT) {
+        float4 a = ((const float4 *)part)[q];
+        for (int s = stride; s < ns; s += stride) {
+            const float4 v = ((const float4 *)(part + (size_t)s * n))[q];
+            a.x += v.x;
+            a.y += v.y;
+            a.z += v.z;
+            a.w += v.w;
+        }
+        out[4 * q] = a.x;
+        out[4 * q + 1] = a.y;
+        out[4 * q + 2] = a.z;
+        out[4 * q + 3] = a.w;
     }
 }
 
@@ -826,37 +941,76 @@ int ensure(void **p, size_t *have, size_t bytes)
     return TVSPEC_OK;
 }
 
-template <int NF>
+template <int NF, int CC, int WAVES>
+void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
+                   int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+{
+    const int tiles_x = (W + kTileX - 1) / kTileX;
+    const int tiles_y = (H + 2 * WAVES - 1) / (2 * WAVES);
+    const dim3 grid((unsigned)((long long)tiles_x * tiles_y * B), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
+    if (f32)
+        hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
+                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y);
+    else
+        hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
+                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y);
+}
+
+// Four waves per workgroup (8 x 32 pixel tiles): 8-wave workgroups
+// (16 x 32) were measured slower on every layer of the network (half the
+// workgroups per CU, barriers over twice the waves).
+template <int NF, int CC>
 void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                  int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
 {
-    const long long P = (long long)B * H * W;
-    const dim3 grid((unsigned)((P + kConvPix - 1) / kConvPix), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
-    if (f32)
-        hipLaunchKernelGGL((k_conv3x3<true, NF>), grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin,
-                           Cout, relu);
-    else
-        hipLaunchKernelGGL((k_conv3x3<false, NF>), grid, dim3(kT), 0, st, x, w, bias, mask, oscale, y, B, H, W, Cin,
-                           Cout, relu);
+    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale);
 }
 
-// Column fragments per wave: 6 (96 channels) unless the layer is narrower.
+// Column fragments per wave: the largest of 6, 4, 3, 2, 1 that divides
+// Cout / 16 (no partly empty column blocks), 6 when none does.
 int conv_nf(int Cout)
 {
-    if (Cout <= 16)
-        return 1;
-    if (Cout <= 48)
-        return 3;
-    return 6;
+    const int n = (Cout + 15) / 16;
+    for (int nf : {6, 4, 3, 2})
+        if (n % nf == 0)
+            return nf;
+    return n == 1 ? 1 : 6;
+}
+
+// Input channels per LDS chunk: 32 if it divides Cin (fewer registers than
+// 48: two workgroups per CU at 96 output channels), else 48, 16 or 8.
+int conv_cc(int Cin)
+{
+    for (int cc : {32, 48, 16})
+        if (Cin % cc == 0)
+            return cc;
+    return 8;
+}
+
+template <int NF>
+void conv_launch_cc(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
+                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+{
+    switch (conv_cc(Cin)) {
+    case 48: conv_launch<NF, 48>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    }
 }
 
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
              const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr)
 {
-    switch (conv_nf(Cout)) {
-    case 1: conv_launch<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 3: conv_launch<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    default: conv_launch<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    int nf = conv_nf(Cout);
+    if (nf == 6 && conv_cc(Cin) == 48)
+        nf = 3;  // 48-channel chunks and 96 columns need ~200 VGPRs: one wave per SIMD
+    switch (nf) {
+    case 1: conv_launch_cc<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 2: conv_launch_cc<2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 3: conv_launch_cc<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 4: conv_launch_cc<4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    default: conv_launch_cc<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
     }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
@@ -869,6 +1023,19 @@ int conv_dgrad(Work &wk, const __bf16 *dy, int B, int H, int W, int Cout, const 
     TVSPEC_TRY(ensure((void **)&wk.wd, &wk.wd_bytes, nw * sizeof(__bf16)));
     hipLaunchKernelGGL(k_flip_transpose, dim3(grid_for((long long)nw)), dim3(kT), 0, st, w, wk.wd, Cout, Cin);
     return conv_fwd(dy, B, H, W, Cout, wk.wd, nullptr, Cin, 0, mask, dx, false, st);
+}
+
+// out[q] = fixed-order sum of the ns rows of part [ns][n] (overwrites part).
+void reduce_rows(float *part, int ns, size_t n, float *out, hipStream_t st)
+{
+    const long long n4 = (long long)(n / 4);
+    int stride = 1;
+    if (ns > kRowGroup) {
+        const int groups = (ns + kRowGroup - 1) / kRowGroup;
+        hipLaunchKernelGGL(k_reduce_groups, dim3(grid_for(n4), groups), dim3(kT), 0, st, part, ns, n);
+        stride = kRowGroup;
+    }
+    hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(n4)), dim3(kT), 0, st, part, ns, stride, n, out);
 }
 
 int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, float *dw,
@@ -890,9 +1057,9 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
     float *bp = db ? wk.part + (size_t)ns * n : nullptr;
     hipLaunchKernelGGL(k_wgrad, dim3(tk, to, (unsigned)ns), dim3(kT), 0, st, x, dy, wk.part, bp, B, H, W, Cin, Cout,
                        cps);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for((long long)n)), dim3(kT), 0, st, wk.part, (int)ns, n, dw);
+    reduce_rows(wk.part, (int)ns, n, dw, st);
     if (db)
-        hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(Cout)), dim3(kT), 0, st, bp, (int)ns, (size_t)Cout, db);
+        reduce_rows(bp, (int)ns, (size_t)Cout, db, st);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }

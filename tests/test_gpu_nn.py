@@ -56,7 +56,9 @@ def to_bf16_np(a):
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout,relu", [(2, 13, 19, 8, 16, False), (1, 9, 33, 48, 48, True),
                                                  (2, 16, 16, 144, 96, True), (1, 7, 5, 24, 64, False),
-                                                 (2, 32, 40, 96, 192, True), (1, 24, 24, 576, 192, False)])
+                                                 (2, 32, 40, 96, 192, True), (1, 24, 24, 576, 192, False),
+                                                 # large grids: 8-wave workgroups
+                                                 (2, 512, 512, 8, 96, True), (1, 512, 1024, 48, 48, False)])
 def test_conv3x3_forward_exact(nn, B, H, W, Cin, Cout, relu):
     rng = np.random.default_rng(Cin * 7 + Cout)
     x = grid16(rng, (B, H, W, Cin))
@@ -75,7 +77,8 @@ def test_conv3x3_forward_exact(nn, B, H, W, Cin, Cout, relu):
 
 
 @pytest.mark.parametrize("B,H,W,Cout,Cin,masked", [(2, 13, 19, 16, 48, False), (1, 10, 12, 48, 144, True),
-                                                   (2, 8, 8, 96, 16, True), (2, 24, 20, 192, 576, True)])
+                                                   (2, 8, 8, 96, 16, True), (2, 24, 20, 192, 576, True),
+                                                   (2, 512, 512, 96, 16, True)])
 def test_conv3x3_dgrad_exact(nn, B, H, W, Cout, Cin, masked):
     rng = np.random.default_rng(Cout * 5 + Cin)
     dy = grid16(rng, (B, H, W, Cout))
@@ -92,7 +95,9 @@ def test_conv3x3_dgrad_exact(nn, B, H, W, Cout, Cin, masked):
 
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout", [(2, 13, 19, 8, 16), (1, 9, 33, 48, 48), (2, 16, 16, 144, 96),
-                                            (3, 24, 40, 16, 8)])
+                                            (3, 24, 40, 16, 8),
+                                            # 512 pixel ranges: the two-stage partial-sum reduction
+                                            (2, 128, 128, 48, 48)])
 def test_conv3x3_wgrad_exact(nn, B, H, W, Cin, Cout):
     rng = np.random.default_rng(Cin * 3 + Cout)
     x = grid16(rng, (B, H, W, Cin))
