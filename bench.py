@@ -197,6 +197,7 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     net = nn.Net(256, 256, batch, seed=seed)
     net.set_output_scale(S.output_scales(btr, rtr))
     net.set_loss_floor(S.LOSS_FLOOR)
+    net.set_grad_clip(S.GRAD_CLIP)
     losses = []
     t1 = time.perf_counter()
     for a in range(0, steps, 250):

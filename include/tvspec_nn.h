@@ -129,6 +129,24 @@ TVSPEC_API int tvspec_net_set_output_scale(tvspec_net *net, const float *scale);
 TVSPEC_API int tvspec_net_set_loss_floor(tvspec_net *net, float kappa);
 
 /*
+ * Gradient-norm clipping for tvspec_net_train_step.  Each step computes the
+ * L2 norm of the whole parameter gradient (fixed-order sum, deterministic)
+ * and compares it with a running average of past norms (seeded by the first
+ * step, then avg <- 0.99 avg + 0.01 min(norm, clip avg)).  If it exceeds
+ * clip x avg, the gradient is scaled down to clip x avg before the Adam
+ * update, so a single outlier batch cannot throw the moments off.  clip = 0
+ * (the default) turns clipping off; otherwise clip must be >= 1.
+ * tvspec_net_set_params resets the running average.
+ */
+TVSPEC_API int tvspec_net_set_grad_clip(tvspec_net *net, float clip);
+
+/*
+ * The last training step's gradient norm, the running average after it and
+ * the factor the gradient was scaled by (host floats; waits for the device).
+ */
+TVSPEC_API int tvspec_net_grad_stats(tvspec_net *net, float *norm, float *avg, float *scale);
+
+/*
  * Forward pass.  f device float32 [B][3][H][W]; out device float32
  * [B][15][H][W] (channel 3j + c = band j of colour c for j < 4, 12 + c =
  * residual of colour c, which is f + scale * the last layer's channel).
@@ -151,7 +169,8 @@ TVSPEC_API int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B
  * One training step on a batch: forward, normalised MSE loss against the
  * decomposition (bands device float64 [B][4][3][H][W], residual device
  * float64 [B][3][H][W], the layouts of tvspec_decompose_batch_dev with four
- * bands), backward, one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8).
+ * bands), backward, gradient-norm clipping if set (tvspec_net_set_grad_clip),
+ * one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8).
  * The loss groups the output into 5 bands of 3 channels (the 4 bands and
  * the residual):  (1/(5B)) sum_b sum_j ||o_bj - t_bj||^2 / (||t_bj||^2 + floor_j) with
  * t_bj the band for j < 4; for the residual group the numerator is

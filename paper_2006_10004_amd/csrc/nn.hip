@@ -853,18 +853,67 @@ __global__ __launch_bounds__(kT) void k_identity_error(const float *__restrict__
 // parameters
 
 // Adam on flat float32 arrays (Kingma and Ba, with bias correction).
+// The gradient is multiplied by *gscale (the clipping factor, 1 without
+// clipping) as it is read.
 __global__ __launch_bounds__(kT) void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                                              float *__restrict__ v, long long n, float lr, float b1, float b2,
-                                             float eps, float c1, float c2)
+                                             float eps, float c1, float c2, const float *__restrict__ gscale)
 {
+    const float gs = *gscale;
     for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
-        const float gq = g[q];
+        const float gq = g[q] * gs;
         const float mq = b1 * m[q] + (1.f - b1) * gq;
         const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
         m[q] = mq;
         v[q] = vq;
         w[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
     }
+}
+
+// Gradient-norm clipping, deterministic: part[blk] = sum of g^2 over the
+// block's grid-stride share (double), then one block totals the partials in
+// order and sets
+//   norm = sqrt(total);  avg <- norm on the first step;
+//   scale = (clip > 0 and norm > clip avg) ? clip avg / norm : 1;
+//   avg <- 0.99 avg + 0.01 min(norm, clip avg)  (clip > 0)
+// state = {norm, avg, scale, steps} (float, float, float, float count).
+constexpr int kNormBlocks = 512;
+
+__global__ __launch_bounds__(kT) void k_sumsq(const float *__restrict__ g, long long n, double *__restrict__ part)
+{
+    __shared__ double sh[kT / 64];
+    double a = 0.0;
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
+        const double x = g[q];
+        a += x * x;
+    }
+    const double t = block_sum_d(a, sh);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(64) void k_clip_scale(const double *__restrict__ part, int nblk, float clip,
+                                                   float *__restrict__ state)
+{
+    if (threadIdx.x != 0)
+        return;
+    double t = 0.0;
+    for (int k = 0; k < nblk; ++k)
+        t += part[k];
+    const float norm = (float)sqrt(t);
+    const bool first = state[3] == 0.f;
+    float avg = first ? norm : state[1];
+    float scale = 1.f;
+    if (clip > 0.f) {
+        const float lim = clip * avg;
+        if (norm > lim && norm > 0.f)
+            scale = lim / norm;
+        avg = 0.99f * avg + 0.01f * fminf(norm, lim);
+    }
+    state[0] = norm;
+    state[1] = avg;
+    state[2] = scale;
+    state[3] += 1.f;
 }
 
 // Layer weights from the flat master vector: wq [cout][9][cin] bf16 (zero
@@ -1107,6 +1156,9 @@ struct tvspec_net {
     float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     long long step = 0;
     float kappa = 0.f;        // loss denominator floor (0: the paper's loss)
+    float gclip = 0.f;        // gradient-norm clip factor (0: off)
+    double *gpart = nullptr;  // [kNormBlocks] sum-of-squares partials
+    float *gstate = nullptr;  // {norm, running average, scale, steps}
     // activations: x0, e1a, e1b, p1, e2a, e2b, p2, e3a, e3b, p3, e4a, e4b, c3, d3a, d3b, c2, d2a, d2b, c1, d1a, d1b
     tvspec::nn::Act A[21];
     float *out = nullptr;     // [P][16]
@@ -1427,6 +1479,10 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->ipart, (size_t)max_batch * n->lblk * sizeof(double));
     if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->gpart, kNormBlocks * sizeof(double));
+    if (rc == TVSPEC_OK)
+        rc = net_alloc(n, (void **)&n->gstate, 4 * sizeof(float));
+    if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->loss, sizeof(float));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->oscale, kOutPad * sizeof(float));
@@ -1436,6 +1492,8 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
         const float ones[kOutPad] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 0.f};
         if (hipMemcpy(n->oscale, ones, sizeof(ones), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(TVSPEC_EDEVICE, "output scale upload failed"));
+        if (hipMemset(n->gstate, 0, 4 * sizeof(float)) != hipSuccess)
+            return cleanup(fail(TVSPEC_EDEVICE, "clip state reset failed"));
     }
     // He-normal weights, zero biases; the output layer starts at zero, so the
     // first outputs are 0 and every band's loss term starts at 1
@@ -1493,6 +1551,7 @@ extern "C" int tvspec_net_set_params(tvspec_net *net, const float *host, long lo
     HIP_TRY(hipMemcpy(net->master, host, (size_t)n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(net->m, 0, (size_t)n * sizeof(float)));
     HIP_TRY(hipMemset(net->v, 0, (size_t)n * sizeof(float)));
+    HIP_TRY(hipMemset(net->gstate, 0, 4 * sizeof(float)));
     net->step = 0;
     TVSPEC_TRY(requant_all(net, nullptr));
     HIP_TRY(hipDeviceSynchronize());
@@ -1526,6 +1585,33 @@ extern "C" int tvspec_net_set_loss_floor(tvspec_net *net, float kappa)
         return fail(TVSPEC_EINVAL, "kappa must be finite and >= 0");
     std::lock_guard<std::mutex> lock(net->mu);
     net->kappa = kappa;
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_set_grad_clip(tvspec_net *net, float clip)
+{
+    g_last_error.clear();
+    if (!net)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    if (!(clip == 0.f || clip >= 1.f) || !std::isfinite(clip))
+        return fail(TVSPEC_EINVAL, "clip must be 0 (off) or finite and >= 1");
+    std::lock_guard<std::mutex> lock(net->mu);
+    net->gclip = clip;
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_grad_stats(tvspec_net *net, float *norm, float *avg, float *scale)
+{
+    g_last_error.clear();
+    if (!net || !norm || !avg || !scale)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lock(net->mu);
+    float h[4];
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(h, net->gstate, sizeof(h), hipMemcpyDeviceToHost));
+    *norm = h[0];
+    *avg = h[1];
+    *scale = h[2];
     return TVSPEC_OK;
 }
 
@@ -1590,8 +1676,10 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
     const float c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
+    hipLaunchKernelGGL(k_sumsq, dim3(kNormBlocks), dim3(kT), 0, st, net->grad, net->nparams, net->gpart);
+    hipLaunchKernelGGL(k_clip_scale, dim3(1), dim3(64), 0, st, net->gpart, kNormBlocks, net->gclip, net->gstate);
     hipLaunchKernelGGL(k_adam, dim3(grid_for(net->nparams)), dim3(kT), 0, st, net->master, net->grad, net->m, net->v,
-                       net->nparams, lr, b1, b2, 1e-8f, c1, c2);
+                       net->nparams, lr, b1, b2, 1e-8f, c1, c2, net->gstate + 2);
     TVSPEC_TRY(requant_all(net, st));
     HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -24,6 +24,8 @@ EXPORTS = (
     "tvspec_net_set_params",
     "tvspec_net_set_output_scale",
     "tvspec_net_set_loss_floor",
+    "tvspec_net_set_grad_clip",
+    "tvspec_net_grad_stats",
     "tvspec_net_forward",
     "tvspec_net_forward_checked",
     "tvspec_net_train_step",
@@ -59,6 +61,10 @@ _lib.tvspec_net_set_output_scale.argtypes = [_vp, _vp]
 _lib.tvspec_net_set_output_scale.restype = _i
 _lib.tvspec_net_set_loss_floor.argtypes = [_vp, _f]
 _lib.tvspec_net_set_loss_floor.restype = _i
+_lib.tvspec_net_set_grad_clip.argtypes = [_vp, _f]
+_lib.tvspec_net_set_grad_clip.restype = _i
+_lib.tvspec_net_grad_stats.argtypes = [_vp, ctypes.POINTER(_f), ctypes.POINTER(_f), ctypes.POINTER(_f)]
+_lib.tvspec_net_grad_stats.restype = _i
 _lib.tvspec_net_forward.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.tvspec_net_forward.restype = _i
 _lib.tvspec_net_forward_checked.argtypes = [_vp, _vp, _i, _vp, _vp, _vp]
@@ -160,6 +166,16 @@ def tvspec_net_set_loss_floor(h, kappa):
     _check(_lib.tvspec_net_set_loss_floor(h, float(kappa)))
 
 
+def tvspec_net_set_grad_clip(h, clip):
+    _check(_lib.tvspec_net_set_grad_clip(h, float(clip)))
+
+
+def tvspec_net_grad_stats(h):
+    n, a, sc = _f(0.0), _f(0.0), _f(0.0)
+    _check(_lib.tvspec_net_grad_stats(h, ctypes.byref(n), ctypes.byref(a), ctypes.byref(sc)))
+    return n.value, a.value, sc.value
+
+
 def tvspec_net_forward(h, f, out, stream=None):
     _check(_lib.tvspec_net_forward(h, f.data_ptr(), f.shape[0], out.data_ptr(), _stream(f, stream)))
 
@@ -246,6 +262,14 @@ class Net:
     def set_loss_floor(self, kappa):
         """Floor of the loss's denominators (see the header); 0 = the paper's loss."""
         tvspec_net_set_loss_floor(self._h, kappa)
+
+    def set_grad_clip(self, clip):
+        """Gradient-norm clipping factor (see the header); 0 = off."""
+        tvspec_net_set_grad_clip(self._h, clip)
+
+    def grad_stats(self):
+        """(norm, running average, scale) of the last training step."""
+        return tvspec_net_grad_stats(self._h)
 
     def forward(self, f, out=None, stream=None, identity=False):
         """f [B,3,H,W] float32 -> [B,15,H,W] float32 (4 bands x 3, residual x 3);

@@ -40,6 +40,10 @@ FLOW = dict(dt=0.005, K=100, iters=150, edges=[0, 1, 2, 4, 100])
 # of the energy of a band at the dataset's RMS size.
 LOSS_FLOOR = 0.05
 
+# Gradient-norm clipping (tvspec_net_set_grad_clip): a step's gradient is
+# scaled down to at most 2x the running average of gradient norms.
+GRAD_CLIP = 2.0
+
 
 def make_images(n, side, seed0, threads=16, spec=None):
     """n seeded images [n, 3, side, side] float32 (spec, by default

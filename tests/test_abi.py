@@ -70,6 +70,15 @@ def test_nn_entry_validation():
         assert lib.tvspec_net_create(H, W, B, 0, ctypes.byref(h)) == -1
     lib.tvspec_net_destroy.argtypes = [vp]
     assert lib.tvspec_net_destroy(None) == 0
+    cf = ctypes.c_float
+    lib.tvspec_net_set_grad_clip.argtypes = [vp, cf]
+    lib.tvspec_net_set_loss_floor.argtypes = [vp, cf]
+    assert lib.tvspec_net_set_grad_clip(None, 2.0) == -1
+    assert lib.tvspec_net_set_loss_floor(None, 0.1) == -1
+    lib.tvspec_net_grad_stats.argtypes = [vp, vp, vp, vp]
+    assert lib.tvspec_net_grad_stats(None, fake, fake, fake) == -1
+    lib.tvspec_net_forward_checked.argtypes = [vp, vp, ci, vp, vp, vp]
+    assert lib.tvspec_net_forward_checked(None, fake, 1, fake, None, None) == -1
 
 
 def test_version(tv):

@@ -255,3 +255,55 @@ def test_adam_step_against_oracle(nn):
     w, _, _ = orc_nn.adam_step(p0.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
     assert np.abs(p1 - w).max() < 1e-6
     net.close()
+
+
+def test_training_is_deterministic(nn):
+    """Every reduction (loss, weight and bias gradients, identity error) runs
+    in a fixed order, so two networks from the same seed, trained on the same
+    batches, end bit for bit equal; so do repeated forward passes."""
+    f, bands, res = inputs(11, B=2, H=64, W=64)
+    ft, bt, rt = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (f, bands, res))
+    params, losses = [], []
+    for _ in range(2):
+        net = nn.Net(64, 64, 2, seed=21)
+        net.set_output_scale(np.linspace(0.05, 0.5, 15).astype(np.float32))
+        net.set_loss_floor(0.05)
+        losses.append([net.train_step(ft, bt, rt, 1e-3) for _ in range(5)])
+        params.append(net.get_params())
+        a = net.forward(ft).cpu().numpy()
+        b = net.forward(ft).cpu().numpy()
+        assert np.array_equal(a, b)
+        net.close()
+    assert losses[0] == losses[1]
+    assert np.array_equal(params[0], params[1])
+
+
+def test_gradient_clipping(nn):
+    """The first step's gradient norm is the norm of the gradient loss_grad
+    returns and seeds the running average (no scaling); a batch whose
+    gradient exceeds clip x average is scaled down to exactly that, and the
+    average moves by 1% towards the clipped norm."""
+    net = nn.Net(32, 32, 2, seed=17)
+    p = net.get_params()
+    net.set_params(p + 0.02 * np.random.default_rng(3).standard_normal(p.size).astype(np.float32))
+    net.set_grad_clip(1.5)
+    f, bands, res = inputs(12)
+    ft, bt, rt = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (f, bands, res))
+    _, g = net.loss_grad(ft, bt, rt)
+    net.train_step(ft, bt, rt, 1e-3)
+    norm, avg, scale = net.grad_stats()
+    ref = np.linalg.norm(g.astype(np.float64))
+    # the average is seeded with the norm, then updated as 0.99 n + 0.01 n
+    # (float32 rounding)
+    assert abs(norm - ref) / ref < 1e-6 and abs(avg - norm) < 1e-6 * norm and scale == 1.0
+    # targets 30x smaller (bands and the residual's difference from f): the
+    # normalised loss then has a much larger gradient
+    net.train_step(ft, bt / 30.0, ft.double() + (rt - ft.double()) / 30.0, 1e-3)
+    norm2, avg2, scale2 = net.grad_stats()
+    lim = np.float32(1.5) * np.float32(avg)
+    assert norm2 > lim
+    assert abs(scale2 - lim / norm2) < 1e-6 * scale2
+    assert abs(avg2 - (0.99 * avg + 0.01 * lim)) < 1e-6 * avg2
+    with pytest.raises(nn.TvspecError):
+        net.set_grad_clip(0.5)
+    net.close()
