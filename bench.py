@@ -323,6 +323,21 @@ def megapixel_serving(net, sides, n_req, seed):
            "band_rel_l1": {k: num[k] / den[k] for k in num},
            "identity_error": {"mean": float(np.mean(ident)), "max": float(np.max(ident))}}
     rec["speedup"] = rec["surrogate"]["MPix_per_s"] / rec["plain"]["MPix_per_s"]
+    # the plain path with the megapixel workload's own flow (dt 0.002, K 300,
+    # 200 iterations, 4 dyadic bands), one request per side: its bands are
+    # not the network's (other time samples), so this is a latency figure
+    flow = dict(dt=0.002, K=300, iters=200, edges=[0, 1, 2, 4, 300])
+    lat_m, mp_m = [], 0.0
+    for side, s in [(side, 60000 + seed + i) for i, side in enumerate(sides)]:
+        f = torch.from_numpy(S.make_images(1, side, s, spec=synth.megapixel_spec(side))).to(dev)
+        _, tm = S.timed(S.decompose_dataset, f, flow)
+        lat_m.append(tm * 1e3)
+        mp_m += side * side / 1e6
+        print("bench: megapixel plain path, its own flow, %dx%d: %.0f ms" % (side, side, tm * 1e3), file=sys.stderr,
+              flush=True)
+    rec["plain_megapixel_flow"] = {"flow": flow, "sides": list(sides), "ms": lat_m,
+                                   "MPix_per_s": mp_m / (sum(lat_m) / 1e3),
+                                   "surrogate_speedup": rec["surrogate"]["MPix_per_s"] / (mp_m / (sum(lat_m) / 1e3))}
     for v in svc.values():
         v.net.close()
     return rec

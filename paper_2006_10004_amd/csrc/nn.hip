@@ -107,7 +107,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                                                         const __bf16 *__restrict__ mask,
                                                         const float *__restrict__ oscale, void *__restrict__ Y, int B,
                                                         int H, int W, int Cin, int Cout, int relu, int tiles_x,
-                                                        int tiles_y)
+                                                        int tiles_y, const __bf16 *__restrict__ Xlow, int Clow)
 {
     using CS = ConvShape<CC, WAVES>;
     constexpr int kPitch = CS::kPitch;
@@ -142,8 +142,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                 const int hx = hp - hy * kHaloX;
                 const int yy = y0 + hy - 1;
                 const int xx = x0 + hx - 1;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    v[j] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + q * CC + 8 * cg);
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                    const int c0 = q * CC + 8 * cg;
+                    if (c0 < Clow)  // the upsampled half of a concatenated input
+                        v[j] = *(const bf16x8 *)(Xlow +
+                                                 ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow +
+                                                 c0);
+                    else
+                        v[j] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) +
+                                                 (c0 - Clow));
+                }
             }
         }
     };
@@ -992,17 +1000,18 @@ int ensure(void **p, size_t *have, size_t bytes)
 
 template <int NF, int CC, int WAVES>
 void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
-                   int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+                   int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
+                   const __bf16 *xlow, int clow)
 {
     const int tiles_x = (W + kTileX - 1) / kTileX;
     const int tiles_y = (H + 2 * WAVES - 1) / (2 * WAVES);
     const dim3 grid((unsigned)((long long)tiles_x * tiles_y * B), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
     if (f32)
         hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
-                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y);
+                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow);
     else
         hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
-                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y);
+                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow);
 }
 
 // Four waves per workgroup (8 x 32 pixel tiles): 8-wave workgroups
@@ -1010,9 +1019,10 @@ void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *
 // workgroups per CU, barriers over twice the waves).
 template <int NF, int CC>
 void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
-                 int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+                 int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
+                 const __bf16 *xlow, int clow)
 {
-    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale);
+    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow);
 }
 
 // Column fragments per wave: the largest of 6, 4, 3, 2, 1 that divides
@@ -1038,28 +1048,36 @@ int conv_cc(int Cin)
 
 template <int NF>
 void conv_launch_cc(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
-                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale)
+                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
+                    const __bf16 *xlow, int clow)
 {
     switch (conv_cc(Cin)) {
-    case 48: conv_launch<NF, 48>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 48: conv_launch<NF, 48>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
     }
 }
 
+// With xlow != nullptr the input is the concatenation [nearest 2x upsampling
+// of xlow ([B][H/2][W/2][clow]), x ([B][H][W][Cin - clow])] along channels,
+// read in place (H, W even; clow a multiple of the chunk width, checked).
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
-             const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr)
+             const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr,
+             const __bf16 *xlow = nullptr, int clow = 0)
 {
+    if (xlow && (clow <= 0 || clow >= Cin || clow % conv_cc(Cin) != 0 || (Cin - clow) % 8 != 0 || H % 2 ||
+                 W % 2))
+        return fail(TVSPEC_EINVAL, "fused concatenation: chunk width must divide the low-resolution channels");
     int nf = conv_nf(Cout);
     if (nf == 6 && conv_cc(Cin) == 48)
         nf = 3;  // 48-channel chunks and 96 columns need ~200 VGPRs: one wave per SIMD
     switch (nf) {
-    case 1: conv_launch_cc<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 2: conv_launch_cc<2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 3: conv_launch_cc<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    case 4: conv_launch_cc<4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
-    default: conv_launch_cc<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale); break;
+    case 1: conv_launch_cc<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 2: conv_launch_cc<2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 3: conv_launch_cc<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 4: conv_launch_cc<4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    default: conv_launch_cc<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
     }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
@@ -1215,7 +1233,10 @@ int requant_all(tvspec_net *n, hipStream_t st)
     return TVSPEC_OK;
 }
 
-int forward(tvspec_net *n, const float *f, int B, hipStream_t st)
+// training: materialise the decoder's concatenations (the weight gradients
+// read them); otherwise the first decoder convolution of each level reads
+// the upsampled lower level and the skip tensor in place.
+int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training)
 {
     Act *A = n->A;
     const int H = n->H, W = n->W;
@@ -1245,14 +1266,21 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st)
     pool(E3B, P3);
     TVSPEC_TRY(conv(6, P3, E4A));
     TVSPEC_TRY(conv(7, E4A, E4B));
-    upcat(E4B, E3B, C3);
-    TVSPEC_TRY(conv(8, C3, D3A));
+    // decoder level: concatenation [upsampled low, skip] -> conv li -> out
+    auto up_conv = [&](int low, int skip, int cat, int li, int out) -> int {
+        if (training) {
+            upcat(low, skip, cat);
+            return conv(li, cat, out);
+        }
+        const Layer &l = n->L[li];
+        return conv_fwd(A[skip].a, B, A[skip].H, A[skip].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false,
+                        st, nullptr, A[low].a, A[low].C);
+    };
+    TVSPEC_TRY(up_conv(E4B, E3B, C3, 8, D3A));
     TVSPEC_TRY(conv(9, D3A, D3B));
-    upcat(D3B, E2B, C2);
-    TVSPEC_TRY(conv(10, C2, D2A));
+    TVSPEC_TRY(up_conv(D3B, E2B, C2, 10, D2A));
     TVSPEC_TRY(conv(11, D2A, D2B));
-    upcat(D2B, E1B, C1);
-    TVSPEC_TRY(conv(12, C1, D1A));
+    TVSPEC_TRY(up_conv(D2B, E1B, C1, 12, D1A));
     TVSPEC_TRY(conv(13, D1A, D1B));
     const Layer &lo = n->L[14];
     TVSPEC_TRY(conv_fwd(A[D1B].a, B, H, W, lo.cin, lo.wq, lo.bias, lo.cout, 0, nullptr, n->out, true, st,
@@ -1624,7 +1652,7 @@ extern "C" int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B
     TVSPEC_TRY(check_batch(net, B));
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
-    TVSPEC_TRY(forward(net, f, B, st));
+    TVSPEC_TRY(forward(net, f, B, st, false));
     const long long HW = (long long)net->H * net->W;
     hipLaunchKernelGGL(k_unpack_output, dim3(net->lblk, B), dim3(kT), 0, st, net->out, f, out, HW,
                        err ? net->ipart : nullptr);
@@ -1648,7 +1676,7 @@ extern "C" int tvspec_net_loss_grad(tvspec_net *net, const float *f, const doubl
     TVSPEC_TRY(check_batch(net, B));
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
-    TVSPEC_TRY(forward(net, f, B, st));
+    TVSPEC_TRY(forward(net, f, B, st, true));
     TVSPEC_TRY(loss_and_grad(net, f, bands, residual, B, st));
     TVSPEC_TRY(backward(net, B, st));
     HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
@@ -1669,7 +1697,7 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
     TVSPEC_TRY(check_batch(net, B));
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
-    TVSPEC_TRY(forward(net, f, B, st));
+    TVSPEC_TRY(forward(net, f, B, st, true));
     TVSPEC_TRY(loss_and_grad(net, f, bands, residual, B, st));
     TVSPEC_TRY(backward(net, B, st));
     net->step += 1;
