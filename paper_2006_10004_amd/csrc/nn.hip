@@ -1025,34 +1025,41 @@ void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w,
     conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow);
 }
 
-// Column fragments per wave: the largest of 6, 4, 3, 2, 1 that divides
-// Cout / 16 (no partly empty column blocks), 6 when none does.
-int conv_nf(int Cout)
+// Column fragments per wave (NF) and input channels per LDS chunk (CC),
+// chosen from measurements on the network's layers: wide layers (NF 6 or 4,
+// 96 or 64 output channels per workgroup) run best with 32-channel chunks;
+// narrow ones (NF <= 3) with 16-channel chunks, whose smaller LDS tile
+// lets more workgroups share a CU.  A wide layer whose Cin is not a multiple
+// of 32 is narrowed to NF <= 3 (wide columns with 16-channel chunks need
+// ~150 VGPRs and were slower).  NF divides Cout / 16 where it can.
+void conv_shape(int Cin, int Cout, int *nf, int *cc)
 {
     const int n = (Cout + 15) / 16;
-    for (int nf : {6, 4, 3, 2})
-        if (n % nf == 0)
-            return nf;
-    return n == 1 ? 1 : 6;
-}
-
-// Input channels per LDS chunk: 32 if it divides Cin (fewer registers than
-// 48: two workgroups per CU at 96 output channels), else 48, 16 or 8.
-int conv_cc(int Cin)
-{
-    for (int cc : {32, 48, 16})
-        if (Cin % cc == 0)
-            return cc;
-    return 8;
+    int f = 1;
+    for (int c : {6, 4, 3, 2})
+        if (n % c == 0) {
+            f = c;
+            break;
+        }
+    if (n > 1 && f == 1)
+        f = 6;  // partly empty last column block
+    if (f >= 4 && Cin % 32 == 0) {
+        *nf = f;
+        *cc = 32;
+        return;
+    }
+    if (f >= 4)
+        f = n % 3 == 0 ? 3 : (n % 2 == 0 ? 2 : 3);
+    *nf = f;
+    *cc = Cin % 16 == 0 ? 16 : 8;
 }
 
 template <int NF>
-void conv_launch_cc(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
-                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
+void conv_launch_cc(int cc, const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias,
+                    int Cout, int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
                     const __bf16 *xlow, int clow)
 {
-    switch (conv_cc(Cin)) {
-    case 48: conv_launch<NF, 48>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    switch (cc) {
     case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
     case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
     default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
@@ -1066,18 +1073,16 @@ int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, con
              const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr,
              const __bf16 *xlow = nullptr, int clow = 0)
 {
-    if (xlow && (clow <= 0 || clow >= Cin || clow % conv_cc(Cin) != 0 || (Cin - clow) % 8 != 0 || H % 2 ||
-                 W % 2))
+    int nf = 1, cc = 8;
+    conv_shape(Cin, Cout, &nf, &cc);
+    if (xlow && (clow <= 0 || clow >= Cin || clow % cc != 0 || (Cin - clow) % 8 != 0 || H % 2 || W % 2))
         return fail(TVSPEC_EINVAL, "fused concatenation: chunk width must divide the low-resolution channels");
-    int nf = conv_nf(Cout);
-    if (nf == 6 && conv_cc(Cin) == 48)
-        nf = 3;  // 48-channel chunks and 96 columns need ~200 VGPRs: one wave per SIMD
     switch (nf) {
-    case 1: conv_launch_cc<1>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 2: conv_launch_cc<2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 3: conv_launch_cc<3>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 4: conv_launch_cc<4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    default: conv_launch_cc<6>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 1: conv_launch_cc<1>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 2: conv_launch_cc<2>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 3: conv_launch_cc<3>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 4: conv_launch_cc<4>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    default: conv_launch_cc<6>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
     }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
