@@ -1032,7 +1032,7 @@ void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w,
 // lets more workgroups share a CU.  A wide layer whose Cin is not a multiple
 // of 32 is narrowed to NF <= 3 (wide columns with 16-channel chunks need
 // ~150 VGPRs and were slower).  NF divides Cout / 16 where it can.
-void conv_shape(int Cin, int Cout, int *nf, int *cc)
+void conv_shape(int B, int H, int W, int Cin, int Cout, int *nf, int *cc)
 {
     const int n = (Cout + 15) / 16;
     int f = 1;
@@ -1043,6 +1043,11 @@ void conv_shape(int Cin, int Cout, int *nf, int *cc)
         }
     if (n > 1 && f == 1)
         f = 6;  // partly empty last column block
+    // a small image gives few pixel tiles: narrower column blocks double the
+    // workgroups where wide ones would leave CUs idle
+    const long long tiles = (long long)B * ((H + 7) / 8) * ((W + kTileX - 1) / kTileX);
+    if (f >= 4 && tiles * ((n + f - 1) / f) < 512)
+        f = n % 3 == 0 ? 3 : (n % 2 == 0 ? 2 : f);
     if (f >= 4 && Cin % 32 == 0) {
         *nf = f;
         *cc = 32;
@@ -1074,7 +1079,7 @@ int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, con
              const __bf16 *xlow = nullptr, int clow = 0)
 {
     int nf = 1, cc = 8;
-    conv_shape(Cin, Cout, &nf, &cc);
+    conv_shape(B, H, W, Cin, Cout, &nf, &cc);
     if (xlow && (clow <= 0 || clow >= Cin || clow % cc != 0 || (Cin - clow) % 8 != 0 || H % 2 || W % 2))
         return fail(TVSPEC_EINVAL, "fused concatenation: chunk width must divide the low-resolution channels");
     switch (nf) {
