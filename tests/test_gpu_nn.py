@@ -171,6 +171,24 @@ def test_network_forward_against_oracle(nn, small_net):
     assert rel(o[:, 12:] - f, ref[:, 12:] - f) < 1e-2
 
 
+def test_network_forward_ragged_size_against_oracle(nn):
+    """24 x 40 images: partial pixel tiles at every level (down to 3 x 5)
+    and the decoder's in-place concatenation of odd-sized low levels."""
+    net = nn.Net(24, 40, 2, seed=8)
+    p = net.get_params()
+    p = p + 0.02 * np.random.default_rng(6).standard_normal(p.size).astype(np.float32)
+    net.set_params(p)
+    f, _, _ = inputs(9, B=2, H=24, W=40)
+    out = net.forward(torch.from_numpy(f).to(DEV))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)
+    y, _ = stored_model().forward(oracle_params(p, nn), to_bf16_np(orc_nn.surrogate_input(f)))
+    ref = orc_nn.surrogate_output(y, f, np.ones(15))
+    assert rel(o[:, :12], ref[:, :12]) < 1e-2, rel(o[:, :12], ref[:, :12])
+    assert rel(o[:, 12:] - f, ref[:, 12:] - f) < 1e-2
+    net.close()
+
+
 @pytest.mark.parametrize("kappa", [0.0, 0.01])
 def test_network_loss_and_gradients_against_oracle(nn, small_net, kappa):
     """kappa: the loss's denominator floor, kappa 3 H W scale_j^2 with the
