@@ -189,6 +189,37 @@ def test_network_forward_ragged_size_against_oracle(nn):
     net.close()
 
 
+@pytest.mark.parametrize("side,B,sample", [(256, 16, (0, 11)), (512, 1, (0,))])
+def test_network_forward_bench_configuration(nn, side, B, sample):
+    """The inference configurations the benchmark times: batch 16 of
+    3 x 256 x 256 shape images, and one 512 x 512 image (the large
+    single-image grids of megapixel serving).  Sampled images of the batch
+    are compared with the oracle, output and identity error."""
+    from paper_2006_10004_amd import surrogate
+    net = nn.Net(side, side, B, seed=13)
+    p = net.get_params()
+    p = p + 0.02 * np.random.default_rng(14).standard_normal(p.size).astype(np.float32)
+    net.set_params(p)
+    scale = np.linspace(0.005, 0.04, 15).astype(np.float32)
+    net.set_output_scale(scale)
+    f = surrogate.make_images(B, side, 300 + side)
+    out, err = net.forward(torch.from_numpy(f).to(DEV), identity=True)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)
+    e = err.cpu().numpy()
+    model = stored_model()
+    params = oracle_params(p, nn)
+    for i in sample:
+        fi = f[i:i + 1]
+        y, _ = model.forward(params, to_bf16_np(orc_nn.surrogate_input(fi)))
+        ref = orc_nn.surrogate_output(y, fi, scale)
+        assert rel(o[i:i + 1, :12], ref[:, :12]) < 1e-2, (i, rel(o[i:i + 1, :12], ref[:, :12]))
+        assert rel(o[i:i + 1, 12:] - fi, ref[:, 12:] - fi) < 1e-2
+        ie = orc_nn.identity_error(fi, o[i:i + 1])[0]
+        assert abs(e[i] - ie) <= 1e-5 * ie, (e[i], ie)
+    net.close()
+
+
 @pytest.mark.parametrize("kappa", [0.0, 0.01])
 def test_network_loss_and_gradients_against_oracle(nn, small_net, kappa):
     """kappa: the loss's denominator floor, kappa 3 H W scale_j^2 with the
