@@ -11,11 +11,12 @@
 // rows 4(l / 16) .. +3.
 //
 //   k_conv3x3      forward (and the input gradient, on flipped, transposed
-//                  weights): a workgroup of 4 waves covers 256 pixels x 16 NF
-//                  output channels (NF = 6, 3 or 1 to fit 96-, 48- and
-//                  16-channel layers); the weight tile goes through LDS,
-//                  activations straight from global memory one step ahead;
-//                  bias, ReLU, a ReLU mask or an output scale fused in the
+//                  weights): a workgroup of 4 waves covers an 8 x 32 pixel
+//                  tile x 16 NF output channels; each chunk of input
+//                  channels is staged in LDS with its halo once and read by
+//                  all 9 taps; the weight tile is double-buffered in LDS;
+//                  the decoder's concatenations can be read in place; bias,
+//                  ReLU, a ReLU mask or an output scale fused in the
 //                  epilogue.
 //   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
 //                  64 output channels x 128 values of k over a range of
