@@ -162,6 +162,14 @@ SERVING = {
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
 
+# The paper's own timing (Table 3; NVIDIA Quadro P6000, 1024 x 1024 images,
+# seconds per image): the model-driven primal-dual GPU implementation against
+# its networks.  Context for the surrogate's speedup only: other hardware,
+# other flow parameters, a plain path ~40x slower than this one.
+PAPER_1024_CONTEXT = {"hardware": "NVIDIA Quadro P6000", "pixels": 1048576, "model_driven_gpu_s": 28.2811,
+                      "tvspecnet_s": 0.0020, "u_tvspecnet_s": 0.0062,
+                      "speedup_tvspecnet": 28.2811 / 0.0020, "speedup_u_tvspecnet": 28.2811 / 0.0062}
+
 
 def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_sides=(1024, 2048), mega_requests=8,
                     seed=11):
@@ -335,6 +343,7 @@ def megapixel_serving(net, sides, n_req, seed):
         mp_m += side * side / 1e6
         print("bench: megapixel plain path, its own flow, %dx%d: %.0f ms" % (side, side, tm * 1e3), file=sys.stderr,
               flush=True)
+    rec["paper_context"] = dict(PAPER_1024_CONTEXT)
     rec["plain_megapixel_flow"] = {"flow": flow, "sides": list(sides), "ms": lat_m,
                                    "MPix_per_s": mp_m / (sum(lat_m) / 1e3),
                                    "surrogate_speedup": rec["surrogate"]["MPix_per_s"] / (mp_m / (sum(lat_m) / 1e3))}
