@@ -497,9 +497,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the decomposition of one image is "
-              "not sharded across GPUs (see the sharding paragraph of the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (images and channels are independent "
+              "decompositions and would shard across GPUs without communication; one image "
+              "is not split). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
