@@ -482,9 +482,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--pdhg-steps", type=int, default=3,
                     help="also time this many decompositions with the primal-dual solver (0 = skip)")
-    ap.add_argument("--sur-train-images", type=int, default=2048,
+    ap.add_argument("--sur-train-images", type=int, default=8192,
                     help="training images of the learned surrogate (0 = skip the surrogate)")
-    ap.add_argument("--sur-steps", type=int, default=3000, help="Adam steps of the surrogate's training")
+    ap.add_argument("--sur-steps", type=int, default=6000, help="Adam steps of the surrogate's training")
     ap.add_argument("--sur-forward-only", type=int, default=0, metavar="N",
                     help="instead of the benchmark, time N forward passes of the surrogate network "
                          "(batch 16 of 3x256x256) and print that record")
