@@ -217,9 +217,15 @@ TVSPEC_API int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, i
  * A server owns a worker thread, one pool of device memory of budget_bytes
  * for the requests' working state, and one stream per size bucket (requests
  * with equal H, W, C and inner_iters).  A submitted request waits in a FIFO
- * queue until its working state fits in the pool and its bucket has a free
- * slot; it is then admitted at the bucket's next step boundary and advances
- * one ROF solve per bucket step alongside the bucket's other requests.
+ * queue until its working state fits in the pool and its bucket runs fewer
+ * than its cap of requests -- as many as fill the device on their own
+ * (16 workgroups per compute unit, one per 32 x 32 tile and channel): two
+ * for 3 x 1024 x 1024, 86 for 3 x 128 x 128; more would only share the
+ * device and each finish later.  A request held back by its bucket's cap
+ * does not hold back requests of other buckets; a request that does not fit
+ * in memory holds back everything after it.  Once admitted it joins at the
+ * bucket's next step boundary and advances one ROF solve per bucket step
+ * alongside the bucket's other requests.
  * Buckets step concurrently on their streams; requests leave as they
  * complete, which frees their memory and slot for the next admission.
  * Every request's results equal those of tvspec_decompose_dev with the

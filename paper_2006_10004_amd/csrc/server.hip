@@ -13,9 +13,11 @@
 //   retires requests whose completion event has fired (their pool range and
 //       slot become free),
 //   admits queued requests in FIFO order while the head request's working
-//       state fits in the pool and its bucket has a free slot (slot
-//       descriptor and band rows are uploaded through pinned staging, then
-//       the slot is initialised on the bucket's stream),
+//       state fits in the pool (slot descriptor and band rows are uploaded
+//       through pinned staging, then the slot is initialised on the bucket's
+//       stream); a request whose bucket already runs its cap -- as many
+//       requests as fill the device on their own -- is passed over together
+//       with the later requests of its bucket,
 //   enqueues the next step of every bucket with requests in flight, keeping
 //       at most kDepth steps per bucket ahead of the device, and finalises
 //       (S, checks, report) the requests that step completes.
@@ -59,6 +61,8 @@ double ms_between(Clock::time_point a, Clock::time_point b)
 }
 
 constexpr int kDepth = 3;         // bucket steps enqueued ahead of the device
+constexpr int kFillPerCU = 16;    // workgroups per CU that fill the device (run cap; measured
+                                  // 4 and 8 lose ~10% throughput to per-step fixed costs)
 constexpr int kSlotCap = 128;     // slots per bucket table
 constexpr int kTableRound = 4;    // table size rounded up to a multiple of this
 constexpr int kTuneSteps = 3;     // steps timed per autotuner candidate
@@ -152,6 +156,7 @@ struct Bucket {
     hipStream_t st = nullptr;
     SlotDesc *table = nullptr;
     int cap = 0;
+    int run_cap = 1;  // requests that fill the device on their own (see bucket_for)
     std::vector<Request *> slots;
     int in_use = 0;
     int parity = 0;
@@ -244,6 +249,19 @@ int bucket_for(tvspec_server *s, const Request &q, int *out)
     b->cfg = StepConfig{b->H, b->W, b->C, b->iters, s->tau, s->warm, s->ipl, s->precision};
     b->cfg.timed = 0;
     b->cap = std::min(kSlotCap, 65535 / b->C);
+    // Run cap: a step of one request launches (tiles x C) workgroups per tile
+    // launch; once the bucket's requests together fill the device
+    // (kFillPerCU workgroups per CU), more of them only share it and each
+    // finishes later, so the bucket admits at most that many at a time and
+    // the rest wait in the queue in order.
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->dev) != hipSuccess || cus < 1)
+            cus = 256;
+        const long long wgs = (long long)((b->H + 31) / 32) * ((b->W + 31) / 32) * b->C;
+        const long long fill = (long long)kFillPerCU * cus;
+        b->run_cap = (int)std::max(1LL, std::min((long long)b->cap, (fill + wgs - 1) / wgs));
+    }
     b->slots.assign(b->cap, nullptr);
     HIP_TRY(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
     HIP_TRY(hipMalloc((void **)&b->table, (size_t)b->cap * sizeof(SlotDesc)));
@@ -486,14 +504,29 @@ int worker_pass(tvspec_server *s, bool *progressed, bool *busy)
     }
     if (*progressed)
         s->cv_done.notify_all();
-    // admit, FIFO
-    while (!s->queue.empty()) {
-        bool ok = false;
-        TVSPEC_TRY(try_admit(s, s->queue.front(), &ok));
-        if (!ok)
-            break;
-        s->queue.pop_front();
-        *progressed = true;
+    // admit in FIFO order, passing over a request whose bucket already runs
+    // its cap (and the later requests of that bucket, which keep their
+    // order); the first request that does not fit in memory stops admission,
+    // so no later request overtakes it for memory
+    {
+        std::vector<int> capped;
+        for (auto it = s->queue.begin(); it != s->queue.end();) {
+            Request *q = *it;
+            int bi = 0;
+            TVSPEC_TRY(bucket_for(s, *q, &bi));
+            const Bucket &bk = *s->buckets[bi];
+            if (std::find(capped.begin(), capped.end(), bi) != capped.end() || bk.in_use >= bk.run_cap) {
+                capped.push_back(bi);
+                ++it;
+                continue;
+            }
+            bool ok = false;
+            TVSPEC_TRY(try_admit(s, q, &ok));
+            if (!ok)
+                break;
+            it = s->queue.erase(it);
+            *progressed = true;
+        }
     }
     // step
     for (auto &bp : s->buckets) {

@@ -220,6 +220,32 @@ def test_many_requests_reuse_slots_and_memory(tv):
         assert_same(outs[j], r)
 
 
+def test_run_cap_admits_saturating_requests_one_at_a_time(tv):
+    """Three 3 x 2048 x 2048 requests each fill the device several times
+    over (12288 workgroups per launch): the bucket runs them one at a time
+    (peak one of them in flight) while a small request submitted after them
+    is not held back; every result equals the direct path's."""
+    dev = torch.device("cuda:0")
+    big = [torch.from_numpy(image(3, 2048, 2048, 300 + i)).to(dev) for i in range(3)]
+    small = torch.from_numpy(image(1, 64, 64, 310)).to(dev)
+    with tv.Server(1 << 34) as srv:
+        ts, outs = [], []
+        for f in big:  # ~40 ms each on the device
+            t, o = srv.submit(f, 0.004, 20, 40, [0, 1, 20])
+            ts.append(t)
+            outs.append(o)
+        t_small, o_small = srv.submit(small, 0.004, 3, 10, [0, 1, 3])
+        res = wait_all(srv, ts + [t_small])
+        info = srv.info()
+    assert info["completed"] == 4 and info["max_in_flight"] == 2, info
+    # the small request was admitted while the first large one ran
+    assert res[3]["queue_ms"] < res[1]["queue_ms"]
+    for f, o in zip(big, outs):
+        assert_same(o, tv.tvspec_decompose_dev(f, 0.004, 20, 40, [0, 1, 20]))
+    assert_same(o_small, tv.tvspec_decompose_dev(small, 0.004, 3, 10, [0, 1, 3]))
+    torch.cuda.synchronize()
+
+
 def test_server_against_oracle(tv, orc):
     dev = torch.device("cuda:0")
     f = synth.shapes_image(synth.SMALL_64, 0)
