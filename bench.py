@@ -279,6 +279,39 @@ def surrogate_forward_only(reps, batch=16, side=256, seed=11):
                          "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "flops_per_pass": flops}}
 
 
+def surrogate_train_only(steps, batch=16, side=256, seed=11):
+    """`steps` Adam steps (loss floor and gradient clipping as in training)
+    on one batch of `batch` 3 x side^2 shape images with synthetic targets of
+    the decomposition's shapes (kernel cost does not depend on the values):
+    the training step's speed alone; the command to profile its kernels."""
+    import numpy as np
+    import torch
+    from paper_2006_10004_amd import nn, surrogate as S
+
+    dev = torch.device("cuda:0")
+    net = nn.Net(side, side, batch, seed=seed)
+    f = torch.from_numpy(S.make_images(batch, side, 80000 + seed)).to(dev)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    bands = (0.01 * torch.randn((batch, 4, 3, side, side), generator=g, dtype=torch.float64)).to(dev)
+    res = f.double() - bands.sum(dim=1)
+    net.set_output_scale(S.output_scales(bands, res))
+    net.set_loss_floor(S.LOSS_FLOOR)
+    net.set_grad_clip(S.GRAD_CLIP)
+    for _ in range(3):
+        net.train_step(f, bands, res, 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(f, bands, res, 1e-3)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    net.close()
+    flops = 3 * S.conv_flops(side, side) * batch  # forward, input and weight gradients
+    return {"workload": "network training step, batch %d of 3x%dx%d" % (batch, side, side), "steps": steps,
+            "ms_per_step": ms, "images_per_s": batch / (ms / 1e3),
+            "conv_TFLOP_per_s": flops / (ms / 1e3) / 1e12}
+
+
 def megapixel_serving(net, sides, n_req, seed):
     """Megapixel requests served one at a time (each waited for): through the
     surrogate service (identity-error fallback at 1e-2) and through the plain
@@ -488,6 +521,9 @@ def main():
     ap.add_argument("--sur-forward-only", type=int, default=0, metavar="N",
                     help="instead of the benchmark, time N forward passes of the surrogate network "
                          "(batch 16 of 3x256x256) and print that record")
+    ap.add_argument("--sur-train-only", type=int, default=0, metavar="N",
+                    help="instead of the benchmark, time N training steps of the surrogate network "
+                         "(batch 16 of 3x256x256) and print that record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -517,6 +553,9 @@ def main():
 
     if args.sur_forward_only > 0:
         print(json.dumps(surrogate_forward_only(args.sur_forward_only)), flush=True)
+        return
+    if args.sur_train_only > 0:
+        print(json.dumps(surrogate_train_only(args.sur_train_only)), flush=True)
         return
 
     from paper_2006_10004_amd import synth, tvspec
