@@ -277,6 +277,49 @@ def test_full_512_workload_parity(tv, orc):
     check_parity(gpu(tv, f, precision="f32", **kw), r, s_tol=TOL_S32, b_tol=TOL_BANDS_F32)
 
 
+MEGA_FLOW = dict(dt=0.002, iters=200)
+
+
+def batch_one(tv, ft, dt, K, iters, edges):
+    """The batched entry point on one image, as the megapixel benchmark
+    calls it; outputs stay on the device."""
+    o = tv.tvspec_decompose_batch_dev(ft[None].contiguous(), [dt], [K], iters, [edges])[0]
+    torch.cuda.synchronize()
+    return o
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("side", [1024, 2048])
+def test_megapixel_flow_full_size(tv, orc, side):
+    """The megapixel fallback flow (3 channels, 300 shapes of radius up to
+    400, dt 0.002, 200 iterations, 4 dyadic bands) at full size and through
+    the batched entry point the benchmark times. Against the oracle over
+    the first K = 5 steps (every tile and launch of a solve, at the full
+    plane size); over all K = 300 steps through what holds at any size: the
+    identity and mean preservation to float64 round-off, no non-finite
+    values, negation and transposition bit for bit."""
+    f = synth.shapes_image(synth.megapixel_spec(side), 70000 + side)
+    ft = torch.from_numpy(f).to("cuda:0")
+    short = dict(K=5, edges=[0, 1, 2, 4, 5], **MEGA_FLOW)
+    g = batch_one(tv, ft, short["dt"], short["K"], short["iters"], short["edges"])
+    r = orc.decompose(f, short["dt"], short["K"], short["iters"], short["edges"])
+    check_parity({k: v.cpu().numpy() for k, v in g.items()}, r)
+    del g, r
+
+    K, edges = 300, [0, 1, 2, 4, 300]
+    g = batch_one(tv, ft, MEGA_FLOW["dt"], K, MEGA_FLOW["iters"], edges)
+    st = g["stats"].cpu().numpy()
+    assert st[0] <= 1e-12 and st[1] <= 1e-12 and st[2] == 0, st
+    assert torch.all(torch.isfinite(g["S"])) and float(g["S"].abs().max()) > 0
+    gn = batch_one(tv, -ft, MEGA_FLOW["dt"], K, MEGA_FLOW["iters"], edges)
+    assert torch.equal(gn["bands"], -g["bands"]) and torch.equal(gn["residual"], -g["residual"])
+    assert torch.equal(gn["S"], g["S"])
+    del gn
+    gt = batch_one(tv, ft.transpose(1, 2).contiguous(), MEGA_FLOW["dt"], K, MEGA_FLOW["iters"], edges)
+    assert torch.equal(gt["bands"], g["bands"].transpose(2, 3))
+    assert torch.equal(gt["residual"], g["residual"].transpose(1, 2))
+
+
 def test_batch_equals_separate_calls(tv, orc):
     """One batched launch sequence over images with different dt, K and band
     edges gives each image's single-call result bit for bit, and matches the
