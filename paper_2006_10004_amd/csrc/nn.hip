@@ -17,7 +17,8 @@
 //                  all 9 taps; the weight tile is double-buffered in LDS;
 //                  the decoder's concatenations can be read in place; bias,
 //                  ReLU, a ReLU mask or an output scale fused in the
-//                  epilogue.
+//                  epilogue, which leaves through an LDS tile in 16-byte
+//                  pieces.
 //   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
 //                  64 output channels x 128 values of k over a range of
 //                  pixels, stages 64-pixel chunks of dY and of the shifted X
@@ -36,6 +37,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -111,11 +113,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                                                         int tiles_y, const __bf16 *__restrict__ Xlow, int Clow)
 {
     using CS = ConvShape<CC, WAVES>;
+    using OutT = typename std::conditional<F32OUT, float, __bf16>::type;
     constexpr int kPitch = CS::kPitch;
     constexpr int kSteps = CS::kSteps;
     constexpr int kNT = CS::kThreads;
-    __shared__ __attribute__((aligned(16))) __bf16 sX[CS::kHaloPix * kPitch];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][NF * 16 * kBPitch];
+    constexpr int kTilePix = CS::kTileY * kTileX;
+    constexpr int kOC = NF * 16;                                   // output channels of the tile
+    constexpr int kOPitch = (((kOC * (int)sizeof(OutT) + 15) / 16) | 1) * 16;  // epilogue bytes per pixel
+    constexpr int kXBytes = CS::kHaloPix * kPitch * 2;
+    constexpr int kBBytes = NF * 16 * kBPitch * 2;
+    constexpr int kSmem = (kXBytes + 2 * kBBytes > kTilePix * kOPitch) ? kXBytes + 2 * kBBytes : kTilePix * kOPitch;
+    // input chunk and the two weight buffers; after the last step, the
+    // epilogue's output tile in the same memory
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
+    __bf16 *const sX = (__bf16 *)smem;
+    __bf16 *const sB0 = (__bf16 *)(smem + kXBytes);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
@@ -192,7 +204,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
         for (int i = 0; i < kWPT; ++i) {
             const int c = threadIdx.x + i * kNT;
             if (c < kWChunks)
-                *(bf16x8 *)(&sB[buf][(c >> 2) * kBPitch + (c & 3) * 8]) = v[i];
+                *(bf16x8 *)(&sB0[buf * (NF * 16 * kBPitch) + (c >> 2) * kBPitch + (c & 3) * 8]) = v[i];
         }
     };
 
@@ -240,7 +252,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                 a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
 #pragma unroll
             for (int c = 0; c < NF; ++c) {
-                const bf16x8 bfr = *(const bf16x8 *)(&sB[buf][(c * 16 + r16) * kBPitch + 8 * g]);
+                const bf16x8 bfr = *(const bf16x8 *)(&sB0[buf * (NF * 16 * kBPitch) + (c * 16 + r16) * kBPitch + 8 * g]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
@@ -257,34 +269,70 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
         }
     }
 
+    // Epilogue in two phases.  (1) Every lane finishes its fragment values
+    // (bias, ReLU, mask, scale) and writes them to an LDS tile [pixel][channel]
+    // whose pixel pitch is an odd number of 16-byte units, so the four pixels
+    // one write instruction covers fall in distinct banks.  (2) The tile
+    // leaves in 16-byte pieces of consecutive channels of a pixel (whole rows
+    // of consecutive memory when the workgroup holds every channel), or
+    // element by element when the channel counts do not allow 16-byte pieces.
+    // The last step's barrier ended every read of the staging buffers.
+    const int nch = Cout - co0 < kOC ? Cout - co0 : kOC;
 #pragma unroll
     for (int c = 0; c < NF; ++c) {
-        const int co = co0 + c * 16 + r16;
+        const int ch = c * 16 + r16;
+        const int co = co0 + ch;
         if (co >= Cout)
             continue;
         const float bv = bias ? bias[co] : 0.f;
         const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int yy = y0 + 2 * wave + (r >> 1);
+            const int ly = 2 * wave + (r >> 1);
+            const int yy = y0 + ly;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int xx = x0 + 16 * (r & 1) + 4 * g + i;
+                const int lx = 16 * (r & 1) + 4 * g + i;
+                const int xx = x0 + lx;
                 if (yy >= H || xx >= W)
                     continue;
-                const size_t p = ((size_t)b * H + yy) * W + xx;
                 float v = acc[r][c][i] + bv;
                 if (relu)
                     v = v > 0.f ? v : 0.f;
-                if (mask && !((float)mask[p * Cout + co] > 0.f))
+                if (mask && !((float)mask[(((size_t)b * H + yy) * W + xx) * Cout + co] > 0.f))
                     v = 0.f;
                 if (oscale)
                     v *= sv;
-                if constexpr (F32OUT)
-                    ((float *)Y)[p * Cout + co] = v;
-                else
-                    ((__bf16 *)Y)[p * Cout + co] = (__bf16)v;
+                *(OutT *)(smem + (ly * kTileX + lx) * kOPitch + ch * (int)sizeof(OutT)) = (OutT)v;
             }
+        }
+    }
+    __syncthreads();
+    OutT *const Yt = (OutT *)Y;
+    if (nch == kOC && (Cout * (int)sizeof(OutT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0) {
+        constexpr int kG = kOC * (int)sizeof(OutT) / 16;  // 16-byte pieces per pixel (co0 keeps them aligned)
+        for (int e = threadIdx.x; e < kTilePix * kG; e += kNT) {
+            const int pix = e / kG;
+            const int j = e - pix * kG;
+            const int ly = pix / kTileX;
+            const int lx = pix - ly * kTileX;
+            const int yy = y0 + ly;
+            const int xx = x0 + lx;
+            if (yy < H && xx < W)
+                *(uint4 *)((unsigned char *)(Yt + (((size_t)b * H + yy) * W + xx) * Cout + co0) + 16 * j) =
+                    *(const uint4 *)(smem + pix * kOPitch + 16 * j);
+        }
+    } else {
+        for (int e = threadIdx.x; e < kTilePix * nch; e += kNT) {
+            const int pix = e / nch;
+            const int ch = e - pix * nch;
+            const int ly = pix / kTileX;
+            const int lx = pix - ly * kTileX;
+            const int yy = y0 + ly;
+            const int xx = x0 + lx;
+            if (yy < H && xx < W)
+                Yt[(((size_t)b * H + yy) * W + xx) * Cout + co0 + ch] =
+                    *(const OutT *)(smem + pix * kOPitch + ch * (int)sizeof(OutT));
         }
     }
 }
