@@ -122,9 +122,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     constexpr int kOPitch = (((kOC * (int)sizeof(OutT) + 15) / 16) | 1) * 16;  // epilogue bytes per pixel
     constexpr int kXBytes = CS::kHaloPix * kPitch * 2;
     constexpr int kBBytes = NF * 16 * kBPitch * 2;
-    constexpr int kSmem = (kXBytes + 2 * kBBytes > kTilePix * kOPitch) ? kXBytes + 2 * kBBytes : kTilePix * kOPitch;
+    constexpr int kTileBytes = F32OUT ? 0 : kTilePix * kOPitch;
+    constexpr int kSmem = (kXBytes + 2 * kBBytes > kTileBytes) ? kXBytes + 2 * kBBytes : kTileBytes;
     // input chunk and the two weight buffers; after the last step, the
-    // epilogue's output tile in the same memory
+    // epilogue's output tile (bf16 outputs) in the same memory
     __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
     __bf16 *const sX = (__bf16 *)smem;
     __bf16 *const sB0 = (__bf16 *)(smem + kXBytes);
@@ -269,7 +270,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
         }
     }
 
-    // Epilogue in two phases.  (1) Every lane finishes its fragment values
+    // float32 outputs (the network's last layer: 15 channels, 60-byte pixels)
+    // are stored directly, element by element: staging them costs that
+    // kernel an occupancy step and saves nothing measurable.
+    if constexpr (F32OUT) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) {
+            const int co = co0 + c * 16 + r16;
+            if (co >= Cout)
+                continue;
+            const float bv = bias ? bias[co] : 0.f;
+            const float sv = oscale ? oscale[co] : 1.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int yy = y0 + 2 * wave + (r >> 1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int xx = x0 + 16 * (r & 1) + 4 * g + i;
+                    if (yy >= H || xx >= W)
+                        continue;
+                    const size_t p = ((size_t)b * H + yy) * W + xx;
+                    float v = acc[r][c][i] + bv;
+                    if (relu)
+                        v = v > 0.f ? v : 0.f;
+                    if (mask && !((float)mask[p * Cout + co] > 0.f))
+                        v = 0.f;
+                    if (oscale)
+                        v *= sv;
+                    ((float *)Y)[p * Cout + co] = v;
+                }
+            }
+        }
+        return;
+    }
+    // bf16 outputs: epilogue in two phases.  (1) Every lane finishes its fragment values
     // (bias, ReLU, mask, scale) and writes them to an LDS tile [pixel][channel]
     // whose pixel pitch is an odd number of 16-byte units, so the four pixels
     // one write instruction covers fall in distinct banks.  (2) The tile
