@@ -61,6 +61,29 @@ __device__ __forceinline__ bf16x8 zero8()
     return z;
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const bf16x8 global_bf16x8;
+
+// Sixteen zero bytes in global memory (never written): the source of the
+// input loads of halo slots outside the image, so that every wave issues a
+// fixed number of loads.  Kept in the global address space (not constant),
+// so that those loads stay global_load rather than flat loads, which would
+// also count against the LDS wait counter.
+__device__ uint4 kZero16[1] = {{0u, 0u, 0u, 0u}};
+
+// s_waitcnt vmcnt(N) lgkmcnt(0): at most N vector memory operations of this
+// wave outstanding (they complete in issue order) and no LDS operation.
+template <int N> __device__ __forceinline__ void wait_vm_lds()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+// s_waitcnt lgkmcnt(0) alone.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// Keeps the compiler from moving memory operations across this point (it
+// emits no instruction): the wait counts below rely on the issue order.
+__device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
+
 // ---------------------------------------------------------------------------
 // convolution (forward and input gradient)
 
@@ -76,8 +99,9 @@ __device__ __forceinline__ bf16x8 zero8()
 // staged in LDS once, and all 9 taps read their operands from there (each
 // input value leaves HBM/L2 1.2 to 1.3 times instead of 9).  A chunk's
 // 9 CC values of k, tap-major (k = tap CC + c), make ceil(9 CC / 32) steps
-// of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) is
-// double-buffered in LDS, loaded one step ahead.  Wave w computes output
+// of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) goes
+// straight from global memory to LDS (global_load_lds_dwordx4, no registers
+// in flight), two steps ahead into three rotating buffers.  Wave w computes output
 // rows 2w, 2w + 1 (four 16-pixel row fragments) x NF column fragments of
 // v_mfma_f32_16x16x32_bf16.  Measured variants that hold more in flight
 // (8-wave workgroups, 64-wide k stages, weights two steps ahead, operand
@@ -121,14 +145,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     constexpr int kOC = NF * 16;                                   // output channels of the tile
     constexpr int kOPitch = (((kOC * (int)sizeof(OutT) + 15) / 16) | 1) * 16;  // epilogue bytes per pixel
     constexpr int kXBytes = CS::kHaloPix * kPitch * 2;
-    constexpr int kBBytes = NF * 16 * kBPitch * 2;
+    // a weight row (one output channel, 32 k) is five 16-byte slots, four of
+    // data and one of padding; a buffer holds whole waves of slots
+    static_assert(kBPitch == 40, "five 16-byte slots per weight row");
+    constexpr int kWSlots = ((NF * 16 * 5 + kNT - 1) / kNT) * kNT;
+    constexpr int kD = kWSlots / kNT;              // direct loads per wave per step
+    constexpr int kXL = CS::kItemsPerThread;       // input loads per thread per chunk
+    constexpr int kBBytes = kWSlots * 16;
     constexpr int kTileBytes = F32OUT ? 0 : kTilePix * kOPitch;
-    constexpr int kSmem = (kXBytes + 2 * kBBytes > kTileBytes) ? kXBytes + 2 * kBBytes : kTileBytes;
-    // input chunk and the two weight buffers; after the last step, the
+    constexpr int kSmem = (kXBytes + 3 * kBBytes > kTileBytes) ? kXBytes + 3 * kBBytes : kTileBytes;
+    // input chunk and the three weight buffers; after the last step, the
     // epilogue's output tile (bf16 outputs) in the same memory
     __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
     __bf16 *const sX = (__bf16 *)smem;
-    __bf16 *const sB0 = (__bf16 *)(smem + kXBytes);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
@@ -144,11 +173,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     const int nchunks = Cin / CC;
 
     // input staging: item i = (halo pixel i / kGroups, 16-byte group i % kGroups)
+    // (every thread issues kXL loads; slots outside the image or past the
+    // chunk read kZero16)
     auto load_x = [&](int q, bf16x8 *v) {
 #pragma unroll
-        for (int j = 0; j < CS::kItemsPerThread; ++j) {
+        for (int j = 0; j < kXL; ++j) {
             const int i = threadIdx.x + j * kNT;
-            v[j] = zero8();
+            const __bf16 *src = (const __bf16 *)kZero16;
             if (i < CS::kItems) {
                 const int hp = i / CS::kGroups;
                 const int cg = i - hp * CS::kGroups;
@@ -159,14 +190,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                 if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
                     const int c0 = q * CC + 8 * cg;
                     if (c0 < Clow)  // the upsampled half of a concatenated input
-                        v[j] = *(const bf16x8 *)(Xlow +
-                                                 ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow +
-                                                 c0);
+                        src = Xlow + ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow + c0;
                     else
-                        v[j] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) +
-                                                 (c0 - Clow));
+                        src = X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) + (c0 - Clow);
                 }
             }
+            v[j] = *(const global_bf16x8 *)src;
         }
     };
     auto store_x = [&](const bf16x8 *v) {
@@ -180,32 +209,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
             }
         }
     };
-    // weight staging for step s of chunk q: chunk c = t + kNT i is row c / 4
-    // (output channel co0 + c / 4), 8 values of k at (c % 4) * 8 of the step
-    constexpr int kWChunks = NF * 16 * 4;
-    constexpr int kWPT = (kWChunks + kNT - 1) / kNT;
-    auto load_w = [&](int q, int s, bf16x8 *v) {
+    // weight tile of step s of chunk q into buffer bb by direct loads: wave
+    // w fills slots [64 (w kD + j), +64), j < kD; slot u is row u / 5 (output
+    // channel co0 + u / 5), k group u % 5 (8 values of k at 8 (u % 5) of the
+    // step).  Slots no MFMA reads (group 4, rows past 16 NF), rows of
+    // channels >= Cout (they only feed outputs that are not stored) and k
+    // past the chunk (their A operand is zero, and finite weights times zero
+    // add exactly 0) read the first weights instead, so every source is Wt
+    // plus a 32-bit offset.
+    auto dma_w = [&](int q, int s, int bb) {
 #pragma unroll
-        for (int i = 0; i < kWPT; ++i) {
-            const int c = threadIdx.x + i * kNT;
-            v[i] = zero8();
-            if (c < kWChunks) {
-                const int co = co0 + (c >> 2);
-                const int kc = s * 32 + (c & 3) * 8;  // k within the chunk
-                if (co < Cout && kc < 9 * CC) {
-                    const int tap = kc / CC;
-                    const int ch = kc - tap * CC;
-                    v[i] = *(const bf16x8 *)(Wt + (size_t)co * K + tap * Cin + q * CC + ch);
-                }
+        for (int j = 0; j < kD; ++j) {
+            const int u = (wave * kD + j) * 64 + lane;
+            const int row = u / 5;
+            const int grp = u - row * 5;
+            const int co = co0 + row;
+            const int kc = s * 32 + grp * 8;  // k within the chunk
+            int off = 0;
+            if (grp < 4 && row < NF * 16 && co < Cout && kc < 9 * CC) {
+                const int tap = kc / CC;
+                off = co * K + tap * Cin + q * CC + (kc - tap * CC);
             }
-        }
-    };
-    auto store_w = [&](int buf, const bf16x8 *v) {
-#pragma unroll
-        for (int i = 0; i < kWPT; ++i) {
-            const int c = threadIdx.x + i * kNT;
-            if (c < kWChunks)
-                *(bf16x8 *)(&sB0[buf * (NF * 16 * kBPitch) + (c >> 2) * kBPitch + (c & 3) * 8]) = v[i];
+            __builtin_amdgcn_global_load_lds(Wt + off,
+                                             (lds_void *)(smem + kXBytes + bb * kBBytes + (wave * kD + j) * 1024), 16,
+                                             0, 0);
         }
     };
 
@@ -223,24 +250,43 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
         for (int c = 0; c < NF; ++c)
             acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    bf16x8 vx[CS::kItemsPerThread];
-    bf16x8 vw[kWPT];
+    // Pipeline over the steps t = q kSteps + s (T in all): at the start of
+    // step t the next chunk's input goes to registers (s = 0 only), then the
+    // weights of step t + 2 (buffer (t + 2) % 3, last read in step t - 1,
+    // whose closing barrier every wave has passed).  At the end of step t each
+    // wave waits until the weights of step t + 1 have landed: loads complete in
+    // issue order, so it waits until no more are outstanding than it issued
+    // after them (in step t: the input loads when s = 0, and the weights of
+    // step t + 2), then passes the barrier that makes every wave's slots
+    // visible.
+    bf16x8 vx[kXL];
+    const int T = nchunks * kSteps;  // kSteps >= 3: steps 0, 1 are in chunk 0
+    dma_w(0, 0, 0);
+    dma_w(0, 1, 1);
+    order_fence();
     load_x(0, vx);
     store_x(vx);
-    load_w(0, 0, vw);
-    store_w(0, vw);
-    __syncthreads();
-    int buf = 0;
+    wait_vm_lds<0>();
+    __builtin_amdgcn_s_barrier();
+    int bcur = 0;
     for (int q = 0; q < nchunks; ++q) {
         const bool next_chunk = q + 1 < nchunks;
-        if (next_chunk)
-            load_x(q + 1, vx);
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
-            const bool last = s + 1 == kSteps;
-            const bool more = !last || next_chunk;
-            if (more)
-                load_w(last ? q + 1 : q, last ? 0 : s + 1, vw);
+            const int t = q * kSteps + s;
+            const bool issue2 = t + 2 < T;
+            const int bnext = bcur == 0 ? 2 : bcur - 1;  // (t + 2) % 3
+            order_fence();
+            if (s == 0 && next_chunk)
+                load_x(q + 1, vx);
+            order_fence();
+            if (issue2) {
+                if (s + 2 < kSteps)
+                    dma_w(q, s + 2, bnext);
+                else
+                    dma_w(q + 1, s + 2 - kSteps, bnext);
+            }
+            order_fence();
             // operands of step s: k = 32 s + 8 g within the chunk
             const int kc = s * 32 + 8 * g;
             const bool kv = kc < 9 * CC;
@@ -251,22 +297,35 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
+            const unsigned char *sBc = smem + kXBytes + bcur * kBBytes;
 #pragma unroll
             for (int c = 0; c < NF; ++c) {
-                const bf16x8 bfr = *(const bf16x8 *)(&sB0[buf * (NF * 16 * kBPitch) + (c * 16 + r16) * kBPitch + 8 * g]);
+                const bf16x8 bfr = *(const bf16x8 *)(sBc + ((c * 16 + r16) * 5 + g) * 16);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
             }
-            if (more)
-                store_w(buf ^ 1, vw);
-            __syncthreads();
-            buf ^= 1;
+            order_fence();
+            const bool lx = next_chunk && s == 0;
+            if (issue2) {
+                if (lx)
+                    wait_vm_lds<kD + kXL>();
+                else
+                    wait_vm_lds<kD>();
+            } else {
+                if (lx)
+                    wait_vm_lds<kXL>();
+                else
+                    wait_vm_lds<0>();
+            }
+            __builtin_amdgcn_s_barrier();
+            bcur = bcur == 2 ? 0 : bcur + 1;
         }
         if (next_chunk) {
             // every wave has read this chunk's tile (barrier above)
             store_x(vx);
-            __syncthreads();
+            wait_lds();
+            __builtin_amdgcn_s_barrier();
         }
     }
 
