@@ -101,7 +101,8 @@ __device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
 // 9 CC values of k, tap-major (k = tap CC + c), make ceil(9 CC / 32) steps
 // of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) goes
 // straight from global memory to LDS (global_load_lds_dwordx4, no registers
-// in flight), two steps ahead into three rotating buffers.  Wave w computes output
+// in flight), kConvPrefetch steps ahead into kConvPrefetch + 1 rotating
+// buffers.  Wave w computes output
 // rows 2w, 2w + 1 (four 16-pixel row fragments) x NF column fragments of
 // v_mfma_f32_16x16x32_bf16.  Measured variants that hold more in flight
 // (8-wave workgroups, 64-wide k stages, weights two steps ahead, operand
@@ -113,6 +114,7 @@ __device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
 // pixels, fall in distinct banks.
 constexpr int kTileX = 32;
 constexpr int kHaloX = kTileX + 2;
+constexpr int kConvPrefetch = 2;  // steps between issuing a weight tile and using it (3 measured 1.5% slower)
 constexpr int kBPitch = 40;  // LDS row pitch of the weight tile (32 k + 8; 20 dwords: 4 x odd)
 
 template <int CC, int WAVES>
@@ -152,9 +154,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     constexpr int kD = kWSlots / kNT;              // direct loads per wave per step
     constexpr int kXL = CS::kItemsPerThread;       // input loads per thread per chunk
     constexpr int kBBytes = kWSlots * 16;
+    constexpr int kPD = kConvPrefetch;             // weights issued kPD steps ahead
+    constexpr int kNB = kPD + 1;                   // rotating weight buffers
+    static_assert(kPD == 2 || kPD == 3, "prefetch distance 2 or 3");
+    static_assert(CS::kSteps >= kPD, "the prologue's steps lie in the first chunk");
     constexpr int kTileBytes = F32OUT ? 0 : kTilePix * kOPitch;
-    constexpr int kSmem = (kXBytes + 3 * kBBytes > kTileBytes) ? kXBytes + 3 * kBBytes : kTileBytes;
-    // input chunk and the three weight buffers; after the last step, the
+    constexpr int kSmem = (kXBytes + kNB * kBBytes > kTileBytes) ? kXBytes + kNB * kBBytes : kTileBytes;
+    // input chunk and the weight buffers; after the last step, the
     // epilogue's output tile (bf16 outputs) in the same memory
     __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
     __bf16 *const sX = (__bf16 *)smem;
@@ -252,17 +258,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
 
     // Pipeline over the steps t = q kSteps + s (T in all): at the start of
     // step t the next chunk's input goes to registers (s = 0 only), then the
-    // weights of step t + 2 (buffer (t + 2) % 3, last read in step t - 1,
+    // weights of step t + kPD (buffer (t + kPD) % kNB, last read in step t - 1,
     // whose closing barrier every wave has passed).  At the end of step t each
     // wave waits until the weights of step t + 1 have landed: loads complete in
     // issue order, so it waits until no more are outstanding than it issued
-    // after them (in step t: the input loads when s = 0, and the weights of
-    // step t + 2), then passes the barrier that makes every wave's slots
-    // visible.
+    // after them (the weights of steps t + 2 .. t + kPD, and the input loads
+    // issued at the start of this chunk if that was after them, i.e. when s <
+    // kPD - 1), then passes the barrier that makes every wave's slots visible.
     bf16x8 vx[kXL];
-    const int T = nchunks * kSteps;  // kSteps >= 3: steps 0, 1 are in chunk 0
-    dma_w(0, 0, 0);
-    dma_w(0, 1, 1);
+    const int T = nchunks * kSteps;
+#pragma unroll
+    for (int i = 0; i < kPD; ++i)
+        dma_w(0, i, i);
     order_fence();
     load_x(0, vx);
     store_x(vx);
@@ -274,17 +281,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
             const int t = q * kSteps + s;
-            const bool issue2 = t + 2 < T;
-            const int bnext = bcur == 0 ? 2 : bcur - 1;  // (t + 2) % 3
+            const int bnext = bcur == 0 ? kNB - 1 : bcur - 1;  // (t + kPD) % kNB
             order_fence();
             if (s == 0 && next_chunk)
                 load_x(q + 1, vx);
             order_fence();
-            if (issue2) {
-                if (s + 2 < kSteps)
-                    dma_w(q, s + 2, bnext);
+            if (t + kPD < T) {
+                if (s + kPD < kSteps)
+                    dma_w(q, s + kPD, bnext);
                 else
-                    dma_w(q + 1, s + 2 - kSteps, bnext);
+                    dma_w(q + 1, s + kPD - kSteps, bnext);
             }
             order_fence();
             // operands of step s: k = 32 s + 8 g within the chunk
@@ -306,20 +312,25 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                     acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
             }
             order_fence();
-            const bool lx = next_chunk && s == 0;
-            if (issue2) {
-                if (lx)
+            // weights issued after those of step t + 1 (steps t + 2 .. t + kPD)
+            const int nw = (t + 2 < T ? 1 : 0) + (kPD == 3 && t + 3 < T ? 1 : 0);
+            if (next_chunk && s < kPD - 1) {
+                if (nw == 2)
+                    wait_vm_lds<2 * kD + kXL>();
+                else if (nw == 1)
                     wait_vm_lds<kD + kXL>();
                 else
-                    wait_vm_lds<kD>();
-            } else {
-                if (lx)
                     wait_vm_lds<kXL>();
+            } else {
+                if (nw == 2)
+                    wait_vm_lds<2 * kD>();
+                else if (nw == 1)
+                    wait_vm_lds<kD>();
                 else
                     wait_vm_lds<0>();
             }
             __builtin_amdgcn_s_barrier();
-            bcur = bcur == 2 ? 0 : bcur + 1;
+            bcur = bcur == kNB - 1 ? 0 : bcur + 1;
         }
         if (next_chunk) {
             // every wave has read this chunk's tile (barrier above)
@@ -1168,12 +1179,12 @@ void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w,
 }
 
 // Column fragments per wave (NF) and input channels per LDS chunk (CC),
-// chosen from measurements on the network's layers: wide layers (NF 6 or 4,
-// 96 or 64 output channels per workgroup) run best with 32-channel chunks;
-// narrow ones (NF <= 3) with 16-channel chunks, whose smaller LDS tile
-// lets more workgroups share a CU.  A wide layer whose Cin is not a multiple
-// of 32 is narrowed to NF <= 3 (wide columns with 16-channel chunks need
-// ~150 VGPRs and were slower).  NF divides Cout / 16 where it can.
+// chosen from measurements of every (NF, CC) on the network's layers: the
+// widest chunk Cin allows (32, else 16, else 8) is fastest at every NF.  A
+// wide layer (NF 6 or 4, 96 or 64 output channels per workgroup) whose Cin
+// is not a multiple of 32 is narrowed to NF <= 3 (wide columns with narrow
+// chunks were no faster and hold more registers), as is one whose image
+// gives fewer than 512 workgroups.  NF divides Cout / 16 where it can.
 void conv_shape(int B, int H, int W, int Cin, int Cout, int *nf, int *cc)
 {
     const int n = (Cout + 15) / 16;
@@ -1190,15 +1201,13 @@ void conv_shape(int B, int H, int W, int Cin, int Cout, int *nf, int *cc)
     const long long tiles = (long long)B * ((H + 7) / 8) * ((W + kTileX - 1) / kTileX);
     if (f >= 4 && tiles * ((n + f - 1) / f) < 512)
         f = n % 3 == 0 ? 3 : (n % 2 == 0 ? 2 : f);
-    if (f >= 4 && Cin % 32 == 0) {
-        *nf = f;
-        *cc = 32;
-        return;
-    }
-    if (f >= 4)
+    // wide column blocks need 32-channel chunks; the widest chunk the input
+    // allows is the fastest at every width (measured per layer: NF 3 with
+    // 32-channel chunks 10-18% faster than with 16)
+    if (f >= 4 && Cin % 32 != 0)
         f = n % 3 == 0 ? 3 : (n % 2 == 0 ? 2 : 3);
     *nf = f;
-    *cc = Cin % 16 == 0 ? 16 : 8;
+    *cc = Cin % 32 == 0 ? 32 : (Cin % 16 == 0 ? 16 : 8);
 }
 
 template <int NF>
