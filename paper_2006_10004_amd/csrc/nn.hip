@@ -380,8 +380,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     // leaves in 16-byte pieces of consecutive channels of a pixel (whole rows
     // of consecutive memory when the workgroup holds every channel), or
     // element by element when the channel counts do not allow 16-byte pieces.
-    // The last step's barrier ended every read of the staging buffers.
+    // The last step's barrier ended every read of the staging buffers.  Without
+    // an output scale, a ReLU mask is applied in (2) to whole 16-byte pieces,
+    // read beside the output (same layout), instead of element by element in
+    // (1): the masked elements become +0 either way.
     const int nch = Cout - co0 < kOC ? Cout - co0 : kOC;
+    const bool wide = nch == kOC && (Cout * (int)sizeof(OutT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0;
+    const bool late_mask = mask && !oscale && wide && ((uintptr_t)mask & 15) == 0;
 #pragma unroll
     for (int c = 0; c < NF; ++c) {
         const int ch = c * 16 + r16;
@@ -403,7 +408,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                 float v = acc[r][c][i] + bv;
                 if (relu)
                     v = v > 0.f ? v : 0.f;
-                if (mask && !((float)mask[(((size_t)b * H + yy) * W + xx) * Cout + co] > 0.f))
+                if (mask && !late_mask && !((float)mask[(((size_t)b * H + yy) * W + xx) * Cout + co] > 0.f))
                     v = 0.f;
                 if (oscale)
                     v *= sv;
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     }
     __syncthreads();
     OutT *const Yt = (OutT *)Y;
-    if (nch == kOC && (Cout * (int)sizeof(OutT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0) {
+    if (wide) {
         constexpr int kG = kOC * (int)sizeof(OutT) / 16;  // 16-byte pieces per pixel (co0 keeps them aligned)
         for (int e = threadIdx.x; e < kTilePix * kG; e += kNT) {
             const int pix = e / kG;
@@ -422,9 +427,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
             const int lx = pix - ly * kTileX;
             const int yy = y0 + ly;
             const int xx = x0 + lx;
-            if (yy < H && xx < W)
-                *(uint4 *)((unsigned char *)(Yt + (((size_t)b * H + yy) * W + xx) * Cout + co0) + 16 * j) =
-                    *(const uint4 *)(smem + pix * kOPitch + 16 * j);
+            if (yy < H && xx < W) {
+                const size_t o = (((size_t)b * H + yy) * W + xx) * Cout + co0;  // element offset of the pixel's block
+                bf16x8 v = *(const bf16x8 *)(smem + pix * kOPitch + 16 * j);
+                if (late_mask) {
+                    const bf16x8 mv = *(const bf16x8 *)((const unsigned char *)(mask + o) + 16 * j);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (!((float)mv[k] > 0.f))
+                            v[k] = (__bf16)0.0f;
+                }
+                *(bf16x8 *)((unsigned char *)(Yt + o) + 16 * j) = v;
+            }
         }
     } else {
         for (int e = threadIdx.x; e < kTilePix * nch; e += kNT) {
