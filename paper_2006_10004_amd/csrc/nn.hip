@@ -506,10 +506,17 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
     const long long HW = (long long)H * W;
     const bool do_bias = bpart != nullptr && blockIdx.x == 0;
 
-    floatx4 acc[kWK / 16];
+    // wave (wo, wk) = (wave / 2, wave % 2) computes output channels
+    // o0 + 32 wo .. +31 x k values k0 + 64 wk .. +63: 2 x 4 fragments, six
+    // operand reads per eight MFMAs (a 16 x 128 strip per wave needs nine)
+    const int wo = wave >> 1;
+    const int wk = wave & 1;
+    floatx4 acc[2][4];
 #pragma unroll
-    for (int j = 0; j < kWK / 16; ++j)
-        acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
 
     // staging roles: dY, thread t: pixel t / 8 (+32), channels (t % 8) * 8;
@@ -584,29 +591,39 @@ __global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, cons
         }
 #pragma unroll
         for (int kk = 0; kk < kWChunk; kk += 32) {
-            const int ra = wave * 16 + r16;
-            const bf16x8 av = *(const bf16x8 *)(sA + ra * kWPitch + swz(ra, kk + 8 * g));
+            bf16x8 av[2], bv[4];
 #pragma unroll
-            for (int j = 0; j < kWK / 16; ++j) {
-                const int rb = j * 16 + r16;
-                const bf16x8 bv = *(const bf16x8 *)(sB + rb * kWPitch + swz(rb, kk + 8 * g));
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+            for (int a = 0; a < 2; ++a) {
+                const int ra = wo * 32 + a * 16 + r16;
+                av[a] = *(const bf16x8 *)(sA + ra * kWPitch + swz(ra, kk + 8 * g));
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int rb = wk * 64 + j * 16 + r16;
+                bv[j] = *(const bf16x8 *)(sB + rb * kWPitch + swz(rb, kk + 8 * g));
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[a][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[j], acc[a][j], 0, 0, 0);
         }
         __syncthreads();
     }
     float *out = part + (size_t)s * Cout * K;
 #pragma unroll
-    for (int j = 0; j < kWK / 16; ++j) {
-        const int k = k0 + j * 16 + r16;
+    for (int j = 0; j < 4; ++j) {
+        const int k = k0 + wk * 64 + j * 16 + r16;
         if (k >= K)
             continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = o0 + wave * 16 + 4 * g + i;
-            if (o < Cout)
-                out[(size_t)o * K + k] = acc[j][i];
-        }
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = o0 + wo * 32 + a * 16 + 4 * g + i;
+                if (o < Cout)
+                    out[(size_t)o * K + k] = acc[a][j][i];
+            }
     }
     if (do_bias && threadIdx.x < 64 && o0 + (int)threadIdx.x < Cout)
         bpart[(size_t)s * Cout + o0 + threadIdx.x] = bacc;
