@@ -57,7 +57,11 @@ def to_bf16_np(a):
 @pytest.mark.parametrize("B,H,W,Cin,Cout,relu", [(2, 13, 19, 8, 16, False), (1, 9, 33, 48, 48, True),
                                                  (2, 16, 16, 144, 96, True), (1, 7, 5, 24, 64, False),
                                                  (2, 32, 40, 96, 192, True), (1, 24, 24, 576, 192, False),
-                                                 # large grids: 8-wave workgroups
+                                                 # a partly filled channel block (NF 6, 80 channels) and a
+                                                 # full one beside a partial one (112): the epilogue's
+                                                 # element-by-element path
+                                                 (1, 11, 37, 32, 80, True), (2, 9, 20, 16, 112, False),
+                                                 # large grids
                                                  (2, 512, 512, 8, 96, True), (1, 512, 1024, 48, 48, False)])
 def test_conv3x3_forward_exact(nn, B, H, W, Cin, Cout, relu):
     rng = np.random.default_rng(Cin * 7 + Cout)
@@ -78,6 +82,9 @@ def test_conv3x3_forward_exact(nn, B, H, W, Cin, Cout, relu):
 
 @pytest.mark.parametrize("B,H,W,Cout,Cin,masked", [(2, 13, 19, 16, 48, False), (1, 10, 12, 48, 144, True),
                                                    (2, 8, 8, 96, 16, True), (2, 24, 20, 192, 576, True),
+                                                   # 80 input channels: a partly filled output block, the
+                                                   # mask applied while staging
+                                                   (2, 9, 20, 32, 80, True),
                                                    (2, 512, 512, 96, 16, True)])
 def test_conv3x3_dgrad_exact(nn, B, H, W, Cout, Cin, masked):
     rng = np.random.default_rng(Cout * 5 + Cin)
