@@ -136,7 +136,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                                                         const __bf16 *__restrict__ mask,
                                                         const float *__restrict__ oscale, void *__restrict__ Y, int B,
                                                         int H, int W, int Cin, int Cout, int relu, int tiles_x,
-                                                        int tiles_y, const __bf16 *__restrict__ Xlow, int Clow)
+                                                        int tiles_y, const __bf16 *__restrict__ Xlow, int Clow,
+                                                        __bf16 *__restrict__ Ypool)
 {
     using CS = ConvShape<CC, WAVES>;
     using OutT = typename std::conditional<F32OUT, float, __bf16>::type;
@@ -438,6 +439,38 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                             v[k] = (__bf16)0.0f;
                 }
                 *(bf16x8 *)((unsigned char *)(Yt + o) + 16 * j) = v;
+            }
+        }
+        if (Ypool) {
+            // 2 x 2 max pooling of the staged tile (8 x 32 -> 4 x 16 pixels), as
+            // k_maxpool takes it: the window's four values in row-major order,
+            // compared in float (host: H, W even, no mask, every channel block full)
+            constexpr int kPX = kTileX / 2;
+            constexpr int kPY = CS::kTileY / 2;
+            const int H2 = H / 2, W2 = W / 2;
+            for (int e = threadIdx.x; e < kPY * kPX * kG; e += kNT) {
+                const int pp = e / kG;
+                const int j = e - pp * kG;
+                const int py = pp / kPX;
+                const int px = pp - py * kPX;
+                const int yy = y0 / 2 + py;
+                const int xx = x0 / 2 + px;
+                if (yy < H2 && xx < W2) {
+                    const unsigned char *t = smem + (2 * py * kTileX + 2 * px) * kOPitch + 16 * j;
+                    bf16x8 m = *(const bf16x8 *)t;
+                    const bf16x8 v1 = *(const bf16x8 *)(t + kOPitch);
+                    const bf16x8 v2 = *(const bf16x8 *)(t + kTileX * kOPitch);
+                    const bf16x8 v3 = *(const bf16x8 *)(t + (kTileX + 1) * kOPitch);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        float a = (float)m[k];
+                        a = (float)v1[k] > a ? (float)v1[k] : a;
+                        a = (float)v2[k] > a ? (float)v2[k] : a;
+                        a = (float)v3[k] > a ? (float)v3[k] : a;
+                        m[k] = (__bf16)a;
+                    }
+                    *(bf16x8 *)(Ypool + (((size_t)b * H2 + yy) * W2 + xx) * Cout + co0 + 8 * j) = m;
+                }
             }
         }
     } else {
@@ -1185,17 +1218,17 @@ int ensure(void **p, size_t *have, size_t bytes)
 template <int NF, int CC, int WAVES>
 void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                   const __bf16 *xlow, int clow)
+                   const __bf16 *xlow, int clow, __bf16 *ypool)
 {
     const int tiles_x = (W + kTileX - 1) / kTileX;
     const int tiles_y = (H + 2 * WAVES - 1) / (2 * WAVES);
     const dim3 grid((unsigned)((long long)tiles_x * tiles_y * B), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
     if (f32)
         hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
-                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow);
+                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, nullptr);
     else
         hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
-                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow);
+                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, ypool);
 }
 
 // Four waves per workgroup (8 x 32 pixel tiles): 8-wave workgroups
@@ -1204,9 +1237,9 @@ void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *
 template <int NF, int CC>
 void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                  int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                 const __bf16 *xlow, int clow)
+                 const __bf16 *xlow, int clow, __bf16 *ypool)
 {
-    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow);
+    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool);
 }
 
 // Column fragments per wave (NF) and input channels per LDS chunk (CC),
@@ -1244,32 +1277,45 @@ void conv_shape(int B, int H, int W, int Cin, int Cout, int *nf, int *cc)
 template <int NF>
 void conv_launch_cc(int cc, const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias,
                     int Cout, int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                    const __bf16 *xlow, int clow)
+                    const __bf16 *xlow, int clow, __bf16 *ypool)
 {
     switch (cc) {
-    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
+    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
+    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
     }
 }
 
 // With xlow != nullptr the input is the concatenation [nearest 2x upsampling
 // of xlow ([B][H/2][W/2][clow]), x ([B][H][W][Cin - clow])] along channels,
 // read in place (H, W even; clow a multiple of the chunk width, checked).
+// With ypool != nullptr the 2 x 2 max pooling of y ([B][H/2][W/2][Cout],
+// H and W even) is written too: by the convolution's epilogue where its
+// tile allows (bf16, no mask, every channel block full, 16-byte aligned),
+// else by k_maxpool afterwards; the values are the same either way.
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
              const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr,
-             const __bf16 *xlow = nullptr, int clow = 0)
+             const __bf16 *xlow = nullptr, int clow = 0, __bf16 *ypool = nullptr)
 {
     int nf = 1, cc = 8;
     conv_shape(B, H, W, Cin, Cout, &nf, &cc);
     if (xlow && (clow <= 0 || clow >= Cin || clow % cc != 0 || (Cin - clow) % 8 != 0 || H % 2 || W % 2))
         return fail(TVSPEC_EINVAL, "fused concatenation: chunk width must divide the low-resolution channels");
+    if (ypool && (H % 2 || W % 2 || f32 || Cout % 8))
+        return fail(TVSPEC_EINVAL, "pooled output: needs even H, W and bf16 output with Cout a multiple of 8");
+    const bool fuse_pool = ypool && !mask && Cout % (nf * 16) == 0 && ((uintptr_t)y & 15) == 0 &&
+                           ((uintptr_t)ypool & 15) == 0;
+    __bf16 *yp = fuse_pool ? ypool : nullptr;
     switch (nf) {
-    case 1: conv_launch_cc<1>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 2: conv_launch_cc<2>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 3: conv_launch_cc<3>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    case 4: conv_launch_cc<4>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
-    default: conv_launch_cc<6>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow); break;
+    case 1: conv_launch_cc<1>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    case 2: conv_launch_cc<2>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    case 3: conv_launch_cc<3>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    case 4: conv_launch_cc<4>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    default: conv_launch_cc<6>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    }
+    if (ypool && !fuse_pool) {
+        const long long cnt = (long long)B * (H / 2) * (W / 2) * (Cout / 8);
+        hipLaunchKernelGGL(k_maxpool, dim3(grid_for(cnt)), dim3(kT), 0, st, (const __bf16 *)y, ypool, B, H, W, Cout);
     }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
@@ -1437,10 +1483,11 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training)
         const Layer &l = n->L[li];
         return conv_fwd(A[in].a, B, A[in].H, A[in].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false, st);
     };
-    auto pool = [&](int in, int out) {
-        const long long cnt = (long long)B * A[out].H * A[out].W * (A[in].C / 8);
-        hipLaunchKernelGGL(k_maxpool, dim3(grid_for(cnt)), dim3(kT), 0, st, A[in].a, A[out].a, B, A[in].H, A[in].W,
-                           A[in].C);
+    // convolution li followed by 2 x 2 max pooling into `pooled`
+    auto conv_pool = [&](int li, int in, int out, int pooled) {
+        const Layer &l = n->L[li];
+        return conv_fwd(A[in].a, B, A[in].H, A[in].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false, st,
+                        nullptr, nullptr, 0, A[pooled].a);
     };
     auto upcat = [&](int low, int skip, int out) {
         const long long cnt = (long long)B * A[out].H * A[out].W * (A[out].C / 8);
@@ -1448,14 +1495,11 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training)
                            A[out].H, A[out].W, A[low].C, A[skip].C);
     };
     TVSPEC_TRY(conv(0, X0, E1A));
-    TVSPEC_TRY(conv(1, E1A, E1B));
-    pool(E1B, P1);
+    TVSPEC_TRY(conv_pool(1, E1A, E1B, P1));
     TVSPEC_TRY(conv(2, P1, E2A));
-    TVSPEC_TRY(conv(3, E2A, E2B));
-    pool(E2B, P2);
+    TVSPEC_TRY(conv_pool(3, E2A, E2B, P2));
     TVSPEC_TRY(conv(4, P2, E3A));
-    TVSPEC_TRY(conv(5, E3A, E3B));
-    pool(E3B, P3);
+    TVSPEC_TRY(conv_pool(5, E3A, E3B, P3));
     TVSPEC_TRY(conv(6, P3, E4A));
     TVSPEC_TRY(conv(7, E4A, E4B));
     // decoder level: concatenation [upsampled low, skip] -> conv li -> out
