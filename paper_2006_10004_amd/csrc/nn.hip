@@ -14,11 +14,12 @@
 //                  weights): a workgroup of 4 waves covers an 8 x 32 pixel
 //                  tile x 16 NF output channels; each chunk of input
 //                  channels is staged in LDS with its halo once and read by
-//                  all 9 taps; the weight tile is double-buffered in LDS;
-//                  the decoder's concatenations can be read in place; bias,
-//                  ReLU, a ReLU mask or an output scale fused in the
-//                  epilogue, which leaves through an LDS tile in 16-byte
-//                  pieces.
+//                  all 9 taps; the weight tiles go straight from global
+//                  memory to LDS two k steps ahead; the decoder's
+//                  concatenations can be read in place; bias, ReLU, a ReLU
+//                  mask, an output scale and the encoder's 2 x 2 max pooling
+//                  fused in the epilogue, which leaves through an LDS tile in
+//                  16-byte pieces.
 //   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
 //                  64 output channels x 128 values of k over a range of
 //                  pixels, stages 64-pixel chunks of dY and of the shifted X
@@ -102,12 +103,12 @@ __device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
 // of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) goes
 // straight from global memory to LDS (global_load_lds_dwordx4, no registers
 // in flight), kConvPrefetch steps ahead into kConvPrefetch + 1 rotating
-// buffers.  Wave w computes output
-// rows 2w, 2w + 1 (four 16-pixel row fragments) x NF column fragments of
-// v_mfma_f32_16x16x32_bf16.  Measured variants that hold more in flight
-// (8-wave workgroups, 64-wide k stages, weights two steps ahead, operand
-// fragments read a step ahead) were all slower: each costs registers or
-// LDS, and the lost occupancy outweighs the latency they hide.
+// buffers.  Wave w computes output rows 2w, 2w + 1 (four 16-pixel row
+// fragments) x NF column fragments of v_mfma_f32_16x16x32_bf16.  Measured
+// variants that hold more in registers (8-wave workgroups, 64-wide k
+// stages, weights two steps ahead in registers, operand fragments read a
+// step ahead, 48-channel chunks) were all slower: each costs occupancy, and
+// the lost workgroups per CU outweigh the latency they hide.
 //
 // LDS pixel pitch: CC bf16 padded to an odd multiple of 16 bytes, so the
 // 16-byte operand reads of 8 (or 16) consecutive lanes, at consecutive
