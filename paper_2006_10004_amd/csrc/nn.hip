@@ -103,8 +103,9 @@ __device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
 // of 32 (zero-padded); the weight tile of a step (16 NF channels x 32 k) goes
 // straight from global memory to LDS (global_load_lds_dwordx4, no registers
 // in flight), kConvPrefetch steps ahead into kConvPrefetch + 1 rotating
-// buffers.  Wave w computes output rows 2w, 2w + 1 (four 16-pixel row
-// fragments) x NF column fragments of v_mfma_f32_16x16x32_bf16.  Measured
+// buffers.  Wave w computes output rows RPW w .. RPW w + RPW - 1 (2 RPW
+// 16-pixel row fragments; RPW = 2) x NF column fragments of
+// v_mfma_f32_16x16x32_bf16.  Measured
 // variants that hold more in registers (8-wave workgroups, 64-wide k
 // stages, weights two steps ahead in registers, operand fragments read a
 // step ahead, 48-channel chunks) were all slower: each costs occupancy, and
@@ -118,11 +119,11 @@ constexpr int kHaloX = kTileX + 2;
 constexpr int kConvPrefetch = 2;  // steps between issuing a weight tile and using it (3 measured 1.5% slower)
 constexpr int kBPitch = 40;  // LDS row pitch of the weight tile (32 k + 8; 20 dwords: 4 x odd)
 
-template <int CC, int WAVES>
+template <int CC, int WAVES, int RPW>
 struct ConvShape {
     static_assert(CC % 8 == 0 && CC <= 64, "chunk of 8..64 channels");
     static constexpr int kThreads = 64 * WAVES;
-    static constexpr int kTileY = 2 * WAVES;
+    static constexpr int kTileY = RPW * WAVES;    // RPW output rows per wave
     static constexpr int kHaloPix = (kTileY + 2) * kHaloX;
     static constexpr int kPitch = ((CC / 8) % 2 == 1) ? CC : CC + 8;  // bf16 per pixel in LDS
     static constexpr int kSteps = (9 * CC + 31) / 32;
@@ -131,7 +132,7 @@ struct ConvShape {
     static constexpr int kItemsPerThread = (kItems + kThreads - 1) / kThreads;
 };
 
-template <bool F32OUT, int NF, int CC, int WAVES>
+template <bool F32OUT, int NF, int CC, int WAVES, int RPW>
 __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
                                                         const float *__restrict__ bias,
                                                         const __bf16 *__restrict__ mask,
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                                                         int tiles_y, const __bf16 *__restrict__ Xlow, int Clow,
                                                         __bf16 *__restrict__ Ypool)
 {
-    using CS = ConvShape<CC, WAVES>;
+    using CS = ConvShape<CC, WAVES, RPW>;
+    constexpr int kRF = 2 * RPW;  // 16-pixel row fragments per wave
     using OutT = typename std::conditional<F32OUT, float, __bf16>::type;
     constexpr int kPitch = CS::kPitch;
     constexpr int kSteps = CS::kSteps;
@@ -246,14 +248,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
 
     // this lane's row fragments: output row lr = 2 wave + (r >> 1), columns
     // 16 (r & 1) + r16; halo pixel of tap (0, 0)
-    int hbase[4];
+    int hbase[kRF];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        hbase[r] = (2 * wave + (r >> 1)) * kHaloX + 16 * (r & 1) + r16;
+    for (int r = 0; r < kRF; ++r)
+        hbase[r] = (RPW * wave + (r >> 1)) * kHaloX + 16 * (r & 1) + r16;
 
-    floatx4 acc[4][NF];
+    floatx4 acc[kRF][NF];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < kRF; ++r)
 #pragma unroll
         for (int c = 0; c < NF; ++c)
             acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -301,16 +303,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
             const int tap = kv ? kc / CC : 0;
             const int ch = kc - tap * CC;
             const int off = ((tap / 3) * kHaloX + (tap - (tap / 3) * 3)) * kPitch + ch;
-            bf16x8 a[4];
+            bf16x8 a[kRF];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < kRF; ++r)
                 a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
             const unsigned char *sBc = smem + kXBytes + bcur * kBBytes;
 #pragma unroll
             for (int c = 0; c < NF; ++c) {
                 const bf16x8 bfr = *(const bf16x8 *)(sBc + ((c * 16 + r16) * 5 + g) * 16);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < kRF; ++r)
                     acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bfr, acc[r][c], 0, 0, 0);
             }
             order_fence();
@@ -354,8 +356,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
             const float bv = bias ? bias[co] : 0.f;
             const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int yy = y0 + 2 * wave + (r >> 1);
+            for (int r = 0; r < kRF; ++r) {
+                const int yy = y0 + RPW * wave + (r >> 1);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int xx = x0 + 16 * (r & 1) + 4 * g + i;
@@ -398,8 +400,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
         const float bv = bias ? bias[co] : 0.f;
         const float sv = oscale ? oscale[co] : 1.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ly = 2 * wave + (r >> 1);
+        for (int r = 0; r < kRF; ++r) {
+            const int ly = RPW * wave + (r >> 1);
             const int yy = y0 + ly;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -1216,31 +1218,34 @@ int ensure(void **p, size_t *have, size_t bytes)
     return TVSPEC_OK;
 }
 
-template <int NF, int CC, int WAVES>
+template <int NF, int CC, int WAVES, int RPW>
 void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
                    const __bf16 *xlow, int clow, __bf16 *ypool)
 {
     const int tiles_x = (W + kTileX - 1) / kTileX;
-    const int tiles_y = (H + 2 * WAVES - 1) / (2 * WAVES);
+    constexpr int kTileY = RPW * WAVES;
+    const int tiles_y = (H + kTileY - 1) / kTileY;
     const dim3 grid((unsigned)((long long)tiles_x * tiles_y * B), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
     if (f32)
-        hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
+        hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES, RPW>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
                            y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, nullptr);
     else
-        hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
+        hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES, RPW>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
                            oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, ypool);
 }
 
-// Four waves per workgroup (8 x 32 pixel tiles): 8-wave workgroups
-// (16 x 32) were measured slower on every layer of the network (half the
-// workgroups per CU, barriers over twice the waves).
+// Four waves per workgroup, two output rows per wave (8 x 32 pixel tiles):
+// 8-wave workgroups (16 x 32) were measured slower on every layer of the
+// network (half the workgroups per CU, barriers over twice the waves), and so
+// were four rows per wave at NF 3 (fewer operand reads per MFMA, but 2
+// instead of 3 waves per SIMD: forward pass 1.21 against 1.16 ms).
 template <int NF, int CC>
 void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                  int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
                  const __bf16 *xlow, int clow, __bf16 *ypool)
 {
-    conv_launch_w<NF, CC, 4>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool);
+    conv_launch_w<NF, CC, 4, 2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool);
 }
 
 // Column fragments per wave (NF) and input channels per LDS chunk (CC),
