@@ -107,9 +107,10 @@ __device__ __forceinline__ void order_fence() { asm volatile("" ::: "memory"); }
 // 16-pixel row fragments; RPW = 2) x NF column fragments of
 // v_mfma_f32_16x16x32_bf16.  Measured
 // variants that hold more in registers (8-wave workgroups, 64-wide k
-// stages, weights two steps ahead in registers, operand fragments read a
-// step ahead, 48-channel chunks) were all slower: each costs occupancy, and
-// the lost workgroups per CU outweigh the latency they hide.
+// stages, weights two steps ahead in registers, 48-channel chunks) were all
+// slower: each costs occupancy, and the lost workgroups per CU outweigh the
+// latency they hide.  The next step's A fragments are read a step ahead only
+// where the 16 registers cost no occupancy (kPrefA).
 //
 // LDS pixel pitch: CC bf16 padded to an odd multiple of 16 bytes, so the
 // 16-byte operand reads of 8 (or 16) consecutive lanes, at consecutive
@@ -269,6 +270,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     // after them (the weights of steps t + 2 .. t + kPD, and the input loads
     // issued at the start of this chunk if that was after them, i.e. when s <
     // kPD - 1), then passes the barrier that makes every wave's slots visible.
+    // A fragments (input tile) of step s of the current chunk: k = 32 s + 8 g
+    // within the chunk.  The shapes whose occupancy allows the 16 registers
+    // read them one step ahead.
+    constexpr bool kPrefA = NF == 6 || (NF == 3 && CC == 16);
+    auto load_a = [&](int s, bf16x8 *a) {
+        const int kc = s * 32 + 8 * g;
+        const bool kv = kc < 9 * CC;
+        const int tap = kv ? kc / CC : 0;
+        const int ch = kc - tap * CC;
+        const int off = ((tap / 3) * kHaloX + (tap - (tap / 3) * 3)) * kPitch + ch;
+#pragma unroll
+        for (int r = 0; r < kRF; ++r)
+            a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
+    };
+    bf16x8 an[kRF];
     bf16x8 vx[kXL];
     const int T = nchunks * kSteps;
 #pragma unroll
@@ -297,16 +313,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
                     dma_w(q + 1, s + kPD - kSteps, bnext);
             }
             order_fence();
-            // operands of step s: k = 32 s + 8 g within the chunk
-            const int kc = s * 32 + 8 * g;
-            const bool kv = kc < 9 * CC;
-            const int tap = kv ? kc / CC : 0;
-            const int ch = kc - tap * CC;
-            const int off = ((tap / 3) * kHaloX + (tap - (tap / 3) * 3)) * kPitch + ch;
+            // A fragments of step s; with kPrefA those of step s + 1 of the
+            // same chunk are read now too, to land during this step's MFMAs
             bf16x8 a[kRF];
+            if constexpr (kPrefA) {
+                if (s == 0)
+                    load_a(0, a);
+                else {
 #pragma unroll
-            for (int r = 0; r < kRF; ++r)
-                a[r] = kv ? *(const bf16x8 *)(&sX[hbase[r] * kPitch + off]) : zero8();
+                    for (int r = 0; r < kRF; ++r)
+                        a[r] = an[r];
+                }
+                if (s + 1 < kSteps)
+                    load_a(s + 1, an);
+            } else {
+                load_a(s, a);
+            }
             const unsigned char *sBc = smem + kXBytes + bcur * kBBytes;
 #pragma unroll
             for (int c = 0; c < NF; ++c) {
