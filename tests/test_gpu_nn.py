@@ -227,6 +227,40 @@ def test_network_forward_bench_configuration(nn, side, B, sample):
     net.close()
 
 
+@pytest.mark.parametrize("side", [1024, 2048])
+def test_network_forward_megapixel_crops(nn, side):
+    """One megapixel image through a network of that size, as the megapixel
+    service runs it (Net(side, side, 1)).  The network is translation
+    equivariant away from the image border: crops whose offsets are
+    multiples of 8 (so the pooling windows align) give the full image's
+    output wherever the crop edge is more than the receptive field (~52 px)
+    away.  So the interior [64, 192)^2 of a 256 x 256 crop, and [0, 192)^2 of
+    the corner crop that shares the image border, are compared with the
+    oracle network run on the crop."""
+    from paper_2006_10004_amd import surrogate, synth
+    net = nn.Net(side, side, 1, seed=17)
+    p = net.get_params()
+    p = p + 0.02 * np.random.default_rng(18).standard_normal(p.size).astype(np.float32)
+    net.set_params(p)
+    scale = np.linspace(0.005, 0.04, 15).astype(np.float32)
+    net.set_output_scale(scale)
+    f = surrogate.make_images(1, side, 900 + side, spec=synth.megapixel_spec(side))
+    out = net.forward(torch.from_numpy(f).to(DEV))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)
+    net.close()
+    model = stored_model()
+    params = oracle_params(p, nn)
+    for y0, x0, lo in [(0, 0, 0), (side // 2 - 128, side // 2 + 64, 64)]:
+        fc = np.ascontiguousarray(f[:, :, y0:y0 + 256, x0:x0 + 256])
+        y, _ = model.forward(params, to_bf16_np(orc_nn.surrogate_input(fc)))
+        ref = orc_nn.surrogate_output(y, fc, scale)[:, :, lo:192, lo:192]
+        got = o[:, :, y0 + lo:y0 + 192, x0 + lo:x0 + 192]
+        fr = fc[:, :, lo:192, lo:192]
+        assert rel(got[:, :12], ref[:, :12]) < 1e-2, (y0, x0, rel(got[:, :12], ref[:, :12]))
+        assert rel(got[:, 12:] - fr, ref[:, 12:] - fr) < 1e-2
+
+
 @pytest.mark.parametrize("kappa", [0.0, 0.01])
 def test_network_loss_and_gradients_against_oracle(nn, small_net, kappa):
     """kappa: the loss's denominator floor, kappa 3 H W scale_j^2 with the
