@@ -101,17 +101,53 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(f, wl):
-    """Time the FP64 CPU oracle on the full workload (all host threads)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(f, wl, one_thread_steps=12):
+    """Time the FP64 CPU oracle on the full workload (all host threads), and
+    on one thread over the first `one_thread_steps` flow steps of the same
+    workload (a child process with OMP_NUM_THREADS=1), scaled per ROF solve
+    to the full workload."""
+    import subprocess
+    import tempfile
+    import numpy as np
     import oracle
     edges = oracle.dyadic_edges(wl["K"], wl["n_bands"])
     t0 = time.perf_counter()
     oracle.decompose(f, wl["dt"], wl["K"], wl["inner_iters"], edges, tau=wl["tau"])
     sec = time.perf_counter() - t0
     mpix = wl["H"] * wl["W"] * wl["C"] / 1e6
-    return {"value": mpix / sec, "unit": "MPix/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "one full decomposition of the same 512x512 workload (201 ROF solves x 300 "
-                      "iterations), %.1f s" % sec}
+    rec = {"value": mpix / sec, "unit": "MPix/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "one full decomposition of the same %dx%d workload (%d ROF solves x %d "
+                     "iterations), %.1f s" % (wl["H"], wl["W"], wl["K"] + 1, wl["inner_iters"], sec),
+           "cpu_model": cpu_model()}
+    k1 = one_thread_steps
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "f.npy")
+        np.save(path, f)
+        code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; f = np.load(%r); "
+                "t0 = time.perf_counter(); oracle.decompose(f, %r, %d, %d, [0, %d], tau=%r); "
+                "print(time.perf_counter() - t0)" % (ROOT, path, wl["dt"], k1, wl["inner_iters"], k1, wl["tau"]))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        print("one-thread oracle sample failed:\n" + r.stderr[-2000:], file=sys.stderr)
+    else:
+        s1 = float(r.stdout.strip().splitlines()[-1])
+        full1 = s1 * (wl["K"] + 1) / (k1 + 1)
+        rec["one_thread"] = {"value": mpix / full1, "unit": "MPix/s", "cores": 1,
+                             "sample": "the first %d flow steps (%d ROF solves x %d iterations), %.1f s, scaled per "
+                                       "solve to the %d solves of the workload" % (k1, k1 + 1, wl["inner_iters"], s1,
+                                                                                   wl["K"] + 1)}
+    return rec
 
 
 def pdhg_block(f, wl, edges, precision, steps):

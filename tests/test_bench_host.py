@@ -25,3 +25,18 @@ def test_traffic_record_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     other.write_text(open(bench.KERNEL_SOURCE).read() + "\n// edited\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
     assert bench.measured_traffic("mixed", 0) is None
+
+
+def test_cpu_baseline_reports_all_threads_and_one_thread():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2006_10004_amd import synth
+    f = synth.shapes_image(synth.ShapeSpec(32, 40, 1), 3)
+    wl = dict(H=32, W=40, C=1, dt=0.01, K=6, inner_iters=20, n_bands=3, tau=0.248)
+    rec = bench.cpu_baseline(f, wl, one_thread_steps=2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "MPix/s"
+    assert rec["value"] > 0 and rec["cores"] >= 1
+    assert "7 ROF solves x 20 iterations" in rec["sample"]
+    one = rec["one_thread"]
+    assert one["cores"] == 1 and one["value"] > 0
+    assert "3 ROF solves" in one["sample"]
