@@ -20,9 +20,11 @@ citations of the paper are in the C source:
                   ROF solver
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
-closed forms, invariants and brute force, except the finite-iteration
-Chambolle iterate on a general image, which has no closed form (its pins are
-the converged special cases and the invariants).
+closed forms, invariants and brute force.  The finite-iteration path of both
+ROF solvers is pinned by worked examples: the first iterates on a two-level
+2 x 2 image, derived by hand as exact fractions.  A finite-iteration iterate
+on a general image has no closed form.  There the pins are those examples,
+the converged special cases and the invariants.
 """
 import ctypes
 import os

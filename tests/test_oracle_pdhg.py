@@ -11,12 +11,14 @@ decomposition run with it, against what the mathematics fixes:
   - exact invariances of the iteration (constant image, one-homogeneity with
     a factor of 2, transposition) and mean preservation;
   - the decomposition by either solver converging to the same bands.
-The iteration's path at a finite count (the extrapolation theta = 1, the
-start xbar = x = g, returning x rather than xbar) follows Chambolle and
-Pock's Algorithm 1 and has no closed form: parity unpinned for the path (a
-mutation that only changes it, e.g. theta = 0, still reaches the same fixed
-point and passes these pins).  The GPU parity tests check the HIP kernel
-against it step for step.
+  - the iteration's path at a finite count (the extrapolation theta = 1, the
+    start xbar = x = g, returning x rather than xbar, the order of the dual
+    and primal updates), by a worked example: the first iterates of Chambolle
+    and Pock's Algorithm 1 on a two-level 2 x 2 image, derived by hand as
+    exact fractions, once with the dual projection inactive and once with it
+    saturated.  A mutation that only changes the path (theta = 0, another
+    start, returning xbar) reaches the same fixed point and passes every
+    other pin; it fails this one.
 """
 import numpy as np
 import pytest
@@ -137,3 +139,31 @@ def test_decompose_pdhg_invalid_arguments(orc):
         orc.decompose(f, 0.01, 3, 10, [0, 3], solver="admm")
     with pytest.raises(ValueError):
         orc.decompose(f, 0.01, 3, 10, [0, 3], solver="pdhg", sigma=-1.0)
+
+
+# Worked example.  g has two identical rows (1, 0), so the vertical dual
+# component stays 0 and the horizontal one lives at column 0 only (forward
+# differences give 0 at the last column); with y = y[0, 0]:
+#   grad xbar = xbar1 - xbar0,  div y = (y, -y),
+#   y  <- y + sigma (xbar1 - xbar0), scaled back to |y| <= lambda,
+#   x  <- (x + tau div y + tau g) / (1 + tau),   xbar <- 2 x_new - x_old,
+# starting from x = xbar = g, y = 0.  With tau = sigma = 1/2:
+#   lambda = 1 (projection never active):
+#     y = -1/2, -2/3, -2/3, -11/18;  x0 = 5/6, 2/3, 5/9, 1/2
+#   lambda = 3/10 (projection active from the first step, y = -3/10):
+#     x0 = 9/10, 5/6, 71/90
+# (x1 = 1 - x0 throughout, since the mean is preserved).
+_WORKED = {
+    1.0: [(-1 / 2, 5 / 6), (-2 / 3, 2 / 3), (-2 / 3, 5 / 9), (-11 / 18, 1 / 2)],
+    0.3: [(-3 / 10, 9 / 10), (-3 / 10, 5 / 6), (-3 / 10, 71 / 90)],
+}
+
+
+@pytest.mark.parametrize("lam", sorted(_WORKED))
+def test_pdhg_worked_example_first_iterates(orc, lam):
+    g = np.array([[1.0, 0.0], [1.0, 0.0]])
+    for n, (y, x0) in enumerate(_WORKED[lam], start=1):
+        v, yx, yy = orc.rof_pdhg(g, lam, n, tau=0.5, sigma=0.5)
+        np.testing.assert_allclose(v, [[x0, 1 - x0], [x0, 1 - x0]], rtol=0, atol=1e-15, err_msg="x after %d" % n)
+        np.testing.assert_allclose(yx, [[y, 0.0], [y, 0.0]], rtol=0, atol=1e-15, err_msg="y after %d" % n)
+        assert not yy.any()

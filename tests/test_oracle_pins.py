@@ -150,6 +150,34 @@ def test_rof_half_plane_one_step(orc):
     assert np.all(np.abs(px) <= 1.0 + 1e-12)  # dual feasibility |p| <= 1
 
 
+# Worked example of Chambolle's fixed-point iteration (Eq. (8)) at a finite
+# count.  g has two identical rows (1, 0), so p stays horizontal and lives at
+# column 0 only (the gradient is 0 at the last column); with p = p[0, 0]:
+#   div p - g/lambda = (p - 1/lambda, -p),   its gradient h = 1/lambda - 2p,
+#   p <- (p + tau h) / (1 + tau |h|),   v = g - lambda div p = (1 - lambda p, lambda p),
+# from p = 0.  With tau = 1/4, derived by hand as exact fractions:
+#   lambda = 1   (solution (1/2, 1/2), p* = 1/2):  p = 1/5, 7/23, 37/101, 175/431
+#   lambda = 1/5 (solution (4/5, 1/5), p* = 1):    p = 5/9, 55/71, 465/529
+_CHAMBOLLE_WORKED = {
+    1.0: [1 / 5, 7 / 23, 37 / 101, 175 / 431],
+    0.2: [5 / 9, 55 / 71, 465 / 529],
+}
+
+
+@pytest.mark.parametrize("lam", sorted(_CHAMBOLLE_WORKED))
+def test_rof_worked_example_first_iterates(orc, lam):
+    """The finite-count path of the iteration: the update's step, its
+    normalisation and the order of div, g/lambda and grad, which the
+    converged-solution pins do not see."""
+    g = np.array([[1.0, 0.0], [1.0, 0.0]])
+    for n, p in enumerate(_CHAMBOLLE_WORKED[lam], start=1):
+        v, px, py = orc.rof(g, lam, n, tau=0.25)
+        np.testing.assert_allclose(px, [[p, 0.0], [p, 0.0]], rtol=0, atol=1e-15, err_msg="p after %d" % n)
+        assert not py.any()
+        u1 = lam * p
+        np.testing.assert_allclose(v, [[1 - u1, u1], [1 - u1, u1]], rtol=0, atol=1e-15, err_msg="v after %d" % n)
+
+
 def test_rof_duality_gap_certificate(orc):
     """Weak duality certifies the ROF solver independently of how it runs:
     for any dual field with |p| <= 1 and u = g - lambda div p, the gap
