@@ -229,3 +229,39 @@ def test_product_path_never_reaches_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", text, flags=re.M), fn
                 assert "liboracle" not in text and "orc_" not in text, fn
+
+
+BATCH_BAD = [
+    (dict(B=0), "B must be >= 1"),
+    (dict(B=-3), "B must be >= 1"),
+    (dict(B=2, C=40000), "B*C"),
+    (dict(H=1), "H and W"),
+    (dict(iters=0), None),
+    (dict(K1=0), "image 1"),
+    (dict(dt1=float("nan")), "image 1"),
+]
+
+
+@pytest.mark.parametrize("bad,msg", BATCH_BAD)
+def test_batch_entry_validation_without_a_device(bad, msg):
+    """The batched entry rejects an empty batch, oversize batches and any
+    image's invalid parameters with TVSPEC_EINVAL before it touches a
+    pointer or the device (host buffers stand in for device ones here)."""
+    lib = ctypes.CDLL(LIB)
+    a = dict(B=2, H=4, W=5, C=1, iters=3, K1=4, dt1=0.1)
+    a.update(bad)
+    nb = max(a["B"], 2)
+    dt = np.array([0.1, a["dt1"]] + [0.1] * (nb - 2), dtype=np.float64)
+    K = np.array([4, a["K1"]] + [4] * (nb - 2), dtype=np.int32)
+    n_bands = np.ones(nb, dtype=np.int32)
+    edges = np.array([x for k in K for x in (0, k)], dtype=np.int32)
+    buf = np.zeros(64, np.float64)
+    p = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    lib.tvspec_decompose_batch_dev.restype = ctypes.c_int
+    lib.tvspec_last_error.restype = ctypes.c_char_p
+    rc = lib.tvspec_decompose_batch_dev(p(buf), a["B"], a["H"], a["W"], a["C"], a["iters"], p(dt), p(K), p(edges),
+                                        p(n_bands), p(buf), p(buf), p(buf), p(buf), ctypes.c_double(0.248), 0, 2, 0,
+                                        None)
+    assert rc == -1
+    if msg is not None:
+        assert msg in lib.tvspec_last_error().decode()
