@@ -100,10 +100,11 @@ extern "C" {
  *   inner_iters  Chambolle iterations per ROF solve (>= 1)
  *   band_edges   n_bands+1 step indices, 0 = e_0 < ... < e_B = K
  *
- * Errors: TVSPEC_EINVAL for H < 2, W < 2, C < 1, H*W > 2^30, bad dt, K,
- * inner_iters, n_bands, edges or a null pointer; TVSPEC_ENUMERIC if f holds
- * a NaN or infinity (checked on the host before any device work);
- * TVSPEC_ENOMEM; TVSPEC_EDEVICE.  Outputs are unspecified on error.
+ * Errors: TVSPEC_EINVAL for H < 2, W < 2, C < 1, C > 65535, H*W > 2^30,
+ * C*H*W > 2^40, bad dt, K, inner_iters, n_bands, edges or a null pointer;
+ * TVSPEC_ENUMERIC if f holds a NaN or infinity (checked on the host before
+ * any device work); TVSPEC_ENOMEM; TVSPEC_EDEVICE.  Outputs are unspecified
+ * on error.
  */
 TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
                      const int *band_edges, int n_bands, double *bands, double *S,
@@ -200,8 +201,9 @@ TVSPEC_API int tvspec_decompose_pdhg_dev(const float *f, int H, int W, int C, do
  *   other arguments as tvspec_decompose_dev.
  *
  * Ownership and ordering as tvspec_decompose_dev.  Errors: TVSPEC_EINVAL for
- * B < 1, B*C > 65535, or any image's invalid dt, K, n_bands or edges (the
- * message names the image), and as tvspec_decompose_dev otherwise.
+ * B < 1, B*C > 65535, B*C*H*W > 2^40, or any image's invalid dt, K, n_bands
+ * or edges (the message names the image), and as tvspec_decompose_dev
+ * otherwise.
  */
 TVSPEC_API int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, int C, int inner_iters,
                                const double *dt, const int *K, const int *band_edges,
