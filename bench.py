@@ -46,6 +46,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_chambolle_tile_512x512_mixed_traffic.md")
+PDHG_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_pdhg_tile_512x512_mixed_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "engine.hip")
 
 
@@ -73,15 +74,16 @@ def copy_bandwidth(mib=1024, reps=5):
     return gbs
 
 
-def measured_traffic(precision, iters_per_launch):
-    """HBM bytes per tile-kernel launch from the committed counter record, or
-    None when the record is for another configuration or the kernel source
-    has changed since the counters were taken."""
+def measured_traffic(precision, iters_per_launch, record=TRAFFIC_RECORD):
+    """HBM bytes per tile-kernel launch from a committed counter record (the
+    Chambolle tile's by default), or None when the record is for another
+    configuration or the kernel source has changed since the counters were
+    taken."""
     import hashlib
     import re
-    if precision != "mixed" or iters_per_launch not in (0, 8) or not os.path.exists(TRAFFIC_RECORD):
+    if precision != "mixed" or iters_per_launch not in (0, 8) or not os.path.exists(record):
         return None
-    m = re.search(r"```json\s*(\{.*?\})\s*```", open(TRAFFIC_RECORD).read(), flags=re.S)
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(record).read(), flags=re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
@@ -183,8 +185,10 @@ def pdhg_block(f, wl, edges, precision, steps):
     return {"solver": "pdhg (Chambolle-Pock, tau = sigma = 1/sqrt(8))", "ms_per_step": ms,
             "MPix_per_s": px / 1e6 / (ms / 1e3), "steps": steps,
             "roofline": {"kernel": "k_pdhg_tile", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_ms * 1e3,
-                         "bytes_per_launch": per_launch, "launches_per_step": t["launches"]},
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(precision, 0, PDHG_TRAFFIC_RECORD),
+                         "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch,
+                         "launches_per_step": t["launches"]},
             "report": {"recon_err": float(st[0]), "mean_err": float(st[1])}}
 
 

@@ -25,6 +25,19 @@ def test_traffic_record_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     other.write_text(open(bench.KERNEL_SOURCE).read() + "\n// edited\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
     assert bench.measured_traffic("mixed", 0) is None
+    assert bench.measured_traffic("mixed", 0, bench.PDHG_TRAFFIC_RECORD) is None
+
+
+def test_primal_dual_traffic_record():
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = json.loads(open(bench.PDHG_TRAFFIC_RECORD).read().split("```json\n")[1].split("\n```")[0])
+    # the writes are the four float64 planes x, xbar, yx, yy of 512 x 512
+    assert rec["write_kib_per_dispatch"] == 4 * 512 * 512 * 8 / 1024
+    want = (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * rec["write_scale"]) * 1024
+    assert abs(rec["traffic_bytes_per_launch"] - want) < 1024
+    assert bench.measured_traffic("mixed", 0, bench.PDHG_TRAFFIC_RECORD) == rec["traffic_bytes_per_launch"]
+    assert bench.measured_traffic("f32", 0, bench.PDHG_TRAFFIC_RECORD) is None
 
 
 def test_cpu_baseline_reports_all_threads_and_one_thread():
