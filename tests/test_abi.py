@@ -265,3 +265,21 @@ def test_batch_entry_validation_without_a_device(bad, msg):
     assert rc == -1
     if msg is not None:
         assert msg in lib.tvspec_last_error().decode()
+
+
+@pytest.mark.parametrize("module", ["tvspec", "nn"])
+def test_bindings_fail_loudly_without_the_library(tmp_path, module):
+    """A copy of the package without libtvspec.so: importing a binding raises
+    (there is no CPU path to fall back on)."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2006_10004_amd"
+    pkg.mkdir()
+    for fn in os.listdir(os.path.join(ROOT, "paper_2006_10004_amd")):
+        if fn.endswith(".py"):
+            shutil.copy(os.path.join(ROOT, "paper_2006_10004_amd", fn), pkg / fn)
+    r = subprocess.run([sys.executable, "-c", "import paper_2006_10004_amd.%s" % module], cwd=str(tmp_path),
+                       env=dict(os.environ, PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is not built" in r.stderr
