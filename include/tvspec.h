@@ -38,9 +38,14 @@
  * TVSPEC_PRECISION_* below.  The flow state u, its step differences, phi,
  * the bands, S and the reconstruction check are always float64.
  *
- * Threading: calls on one device share that device's scratch memory; calls
- * that overlap in time on one device (different host threads, or different
- * streams) race.  Serialise them (one stream, or one thread).
+ * Threading and streams: the decomposition entry points (tvspec_decompose,
+ * _ex, _dev, _pdhg_dev, _batch_dev) may be called from any host thread and
+ * on any streams.  Calls of one precision mode on one device share that
+ * device's scratch memory; each call's device work is ordered after the
+ * previous call's on the device (its stream waits for an event the previous
+ * call recorded on its own stream), so calls on different streams run one
+ * after the other and never mix their state.  The host is not blocked by
+ * this ordering.  The server (tvspec_server_*) has memory of its own.
  */
 #ifndef TVSPEC_H
 #define TVSPEC_H
@@ -61,7 +66,7 @@ extern "C" {
 /* Return codes. */
 #define TVSPEC_OK 0
 #define TVSPEC_EINVAL (-1)   /* invalid argument; nothing was done on the device */
-#define TVSPEC_ENUMERIC (-2) /* non-finite input value (host entry point only) */
+#define TVSPEC_ENUMERIC (-2) /* non-finite input value (host buffers, or tvspec_decompose_ex with a report) */
 #define TVSPEC_ENOMEM (-3)   /* device or host allocation failed */
 #define TVSPEC_EDEVICE (-4)  /* HIP runtime error; tvspec_last_error() has the text */
 #define TVSPEC_EBUSY (-5)    /* request can never fit the server's memory budget */
@@ -109,6 +114,81 @@ extern "C" {
 TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
                      const int *band_edges, int n_bands, double *bands, double *S,
                      double *residual);
+
+/*
+ * Entry point with an options struct and a per-call report (the device work
+ * and wall time of the call, and the checks of the decomposition).
+ *
+ * args:  the image and the outputs, layouts as above.  f, bands, S, residual
+ *        and stats are host pointers with device_ptrs = 0 (stats may then be
+ *        NULL) and device pointers with device_ptrs = 1 (stats required,
+ *        TVSPEC_NSTATS doubles, filled as by tvspec_decompose_dev);
+ *        band_edges is always a host array.
+ * opt:   NULL = the defaults tvspec_default_options() fills (as
+ *        tvspec_decompose: Chambolle, tau 0.248, cold start, MIXED,
+ *        automatic blocking, host buffers).
+ *          solver            TVSPEC_SOLVER_CHAMBOLLE or TVSPEC_SOLVER_PDHG
+ *          tau, sigma        Chambolle step (0 = 0.248; sigma unused), or
+ *                            the primal-dual steps (both 0 = 1/sqrt(8) each)
+ *          warm_start, precision, iters_per_launch
+ *                            as tvspec_decompose_dev
+ *          device_ptrs       0: host buffers, the call is synchronous;
+ *                            1: device buffers, work enqueued on `stream`
+ *          stream            hipStream_t for device_ptrs = 1 (NULL = null stream)
+ * rep:   NULL = no report.  Otherwise the call waits until its work is
+ *        complete (also with device_ptrs = 1) and fills
+ *          recon_err   max |f - sum of bands - residual|
+ *          mean_err    max over channels of |mean(u_{K+1}) - mean(f_c)|
+ *          nonfinite   number of non-finite values in f
+ *          device_ms   device time from the first to the last kernel of the
+ *                      decomposition (hipEvents on its stream; excludes the
+ *                      host-buffer copies)
+ *          total_ms    host wall time of the whole call
+ *
+ * Errors: as tvspec_decompose_dev, TVSPEC_EINVAL for a bad solver,
+ * device_ptrs or step, and TVSPEC_ENUMERIC for non-finite input: with host
+ * buffers before any device work; with device buffers when a report is
+ * requested (after the work: the outputs are then meaningless; without a
+ * report the count is only in stats[2]).
+ */
+#define TVSPEC_SOLVER_CHAMBOLLE 0
+#define TVSPEC_SOLVER_PDHG 1
+
+typedef struct tvspec_args {
+    const float *f;
+    int H, W, C;
+    double dt;
+    int K;
+    int inner_iters;
+    const int *band_edges;
+    int n_bands;
+    double *bands;
+    double *S;
+    double *residual;
+    double *stats;
+} tvspec_args;
+
+typedef struct tvspec_options {
+    int solver;
+    double tau;
+    double sigma;
+    int warm_start;
+    int precision;
+    int iters_per_launch;
+    int device_ptrs;
+    void *stream;
+} tvspec_options;
+
+typedef struct tvspec_report {
+    double recon_err;
+    double mean_err;
+    double nonfinite;
+    double device_ms;
+    double total_ms;
+} tvspec_report;
+
+TVSPEC_API void tvspec_default_options(tvspec_options *opt);
+TVSPEC_API int tvspec_decompose_ex(const tvspec_args *args, const tvspec_options *opt, tvspec_report *rep);
 
 /*
  * Device entry point with all options.  f, bands, S, residual and stats are

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -25,9 +26,16 @@ namespace {
 // ---------------------------------------------------------------------------
 // per-device state, guarded by g_mu
 
+// One scratch arena per (device, precision).  `done` is recorded on the
+// stream of the last call that used the arena, after its last use; the next
+// call makes its own stream wait for it before touching the arena, so calls
+// on different streams (or threads) are ordered on the device without a host
+// synchronisation.
 struct Arena {
     size_t bytes = 0;
     char *base = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
 };
 
 // Pinned host staging of a slot table and its band rows, and an event marking
@@ -60,6 +68,32 @@ template <typename T> void free_dev(T *&p)
         (void)hipFree((void *)p);
     p = nullptr;
 }
+
+// Order `st` after the previous user of the arena (device-side wait).
+int arena_acquire(Arena &a, hipStream_t st)
+{
+    if (!a.done)
+        HIP_TRY(hipEventCreateWithFlags(&a.done, hipEventDisableTiming));
+    if (a.used)
+        HIP_TRY(hipStreamWaitEvent(st, a.done, 0));
+    return TVSPEC_OK;
+}
+
+// Mark the end of this call's use of the arena on `st`.
+int arena_release(Arena &a, hipStream_t st)
+{
+    HIP_TRY(hipEventRecord(a.done, st));
+    a.used = true;
+    return TVSPEC_OK;
+}
+
+// Releases the arena when the call leaves, also on its error paths (work it
+// enqueued before failing is then still ordered before the next call).
+struct ArenaUse {
+    Arena &a;
+    hipStream_t st;
+    ~ArenaUse() { (void)arena_release(a, st); }
+};
 
 int ensure_arena(Arena &a, size_t bytes)
 {
@@ -143,6 +177,8 @@ int run_batch(const Batch &a)
     const size_t nf_bytes = align256((size_t)a.B * sizeof(unsigned int));
     Arena &ar = g_arena[dev][a.precision];
     TVSPEC_TRY(ensure_arena(ar, table_bytes + rows_bytes + nf_bytes + slots_bytes));
+    TVSPEC_TRY(arena_acquire(ar, a.st));
+    ArenaUse use{ar, a.st};
     SlotDesc *d_table = (SlotDesc *)ar.base;
     int *d_rows = (int *)(ar.base + table_bytes);
     unsigned int *d_nf = (unsigned int *)(ar.base + table_bytes + rows_bytes);
@@ -383,63 +419,182 @@ extern "C" int tvspec_decompose_pdhg_dev(const float *f, int H, int W, int C, do
     return run_batch(a);
 }
 
-extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
-                                const int *band_edges, int n_bands, double *bands, double *S, double *residual)
+extern "C" void tvspec_default_options(tvspec_options *o)
 {
+    if (!o)
+        return;
+    o->solver = TVSPEC_SOLVER_CHAMBOLLE;
+    o->tau = 0.0;
+    o->sigma = 0.0;
+    o->warm_start = 0;
+    o->precision = TVSPEC_DEFAULT_PRECISION;
+    o->iters_per_launch = 0;
+    o->device_ptrs = 0;
+    o->stream = nullptr;
+}
+
+namespace {
+
+// Events around the device work of one call (report timing); destroyed on
+// every exit path.
+struct CallEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~CallEvents()
+    {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+    }
+};
+
+} // namespace
+
+extern "C" int tvspec_decompose_ex(const tvspec_args *args, const tvspec_options *opt, tvspec_report *rep)
+{
+    const auto t_start = std::chrono::steady_clock::now();
     g_last_error.clear();
-    if (!f || !band_edges || !bands || !S || !residual)
+    if (!args)
         return fail(TVSPEC_EINVAL, "null pointer argument");
-    TVSPEC_TRY(validate_shape(1, H, W, C, inner_iters));
-    TVSPEC_TRY(validate_image(dt, K, band_edges, n_bands));
-    const size_t n_all = (size_t)H * W * C;
-    for (size_t q = 0; q < n_all; ++q)
-        if (!std::isfinite(f[q]))
-            return fail(TVSPEC_ENUMERIC, "input holds a NaN or infinity");
+    tvspec_options o;
+    tvspec_default_options(&o);
+    if (opt)
+        o = *opt;
+    const tvspec_args &x = *args;
+    if (o.device_ptrs != 0 && o.device_ptrs != 1)
+        return fail(TVSPEC_EINVAL, "device_ptrs must be 0 or 1");
+    if (!x.f || !x.band_edges || !x.bands || !x.S || !x.residual || (o.device_ptrs && !x.stats))
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    TVSPEC_TRY(validate_shape(1, x.H, x.W, x.C, x.inner_iters));
+    TVSPEC_TRY(validate_image(x.dt, x.K, x.band_edges, x.n_bands));
+    double tau = o.tau, sigma = o.sigma;
+    int solver = kSolverChambolle;
+    if (o.solver == TVSPEC_SOLVER_PDHG) {
+        solver = kSolverPDHG;
+        if (tau == 0.0 && sigma == 0.0)
+            tau = sigma = TVSPEC_PDHG_DEFAULT_STEP;
+        if (!std::isfinite(tau) || !std::isfinite(sigma) || !(tau > 0.0) || !(sigma > 0.0) ||
+            tau * sigma * 8.0 > 1.0 + 1e-12)
+            return fail(TVSPEC_EINVAL, "PDHG steps need tau > 0, sigma > 0 and 8 tau sigma <= 1");
+        TVSPEC_TRY(validate_opts(TVSPEC_DEFAULT_TAU, o.warm_start, o.precision, o.iters_per_launch));
+    } else if (o.solver == TVSPEC_SOLVER_CHAMBOLLE) {
+        if (tau == 0.0)
+            tau = TVSPEC_DEFAULT_TAU;
+        TVSPEC_TRY(validate_opts(tau, o.warm_start, o.precision, o.iters_per_launch));
+    } else {
+        return fail(TVSPEC_EINVAL, "solver must be TVSPEC_SOLVER_CHAMBOLLE or TVSPEC_SOLVER_PDHG");
+    }
+    const size_t n_all = (size_t)x.H * x.W * x.C;
+    if (!o.device_ptrs)
+        for (size_t q = 0; q < n_all; ++q)
+            if (!std::isfinite(x.f[q]))
+                return fail(TVSPEC_ENUMERIC, "input holds a NaN or infinity");
 
     std::lock_guard<std::mutex> lock(g_mu);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= kMaxDevices)
         return fail(TVSPEC_EDEVICE, "device index out of range");
-    HostIO &h = g_hostio[dev];
-    if (!h.stream)
-        HIP_TRY(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
-    const size_t nb_n = (size_t)n_bands * n_all;
-    const size_t s_n = (size_t)C * K;
-    TVSPEC_TRY(grow(h.f, h.f_n, n_all));
-    TVSPEC_TRY(grow(h.bands, h.bands_n, nb_n));
-    TVSPEC_TRY(grow(h.S, h.s_n, s_n));
-    TVSPEC_TRY(grow(h.res, h.r_n, n_all));
-    if (!h.stats)
-        HIP_TRY(hipMalloc((void **)&h.stats, TVSPEC_NSTATS * sizeof(double)));
-
-    HIP_TRY(hipMemcpyAsync(h.f, f, n_all * sizeof(float), hipMemcpyHostToDevice, h.stream));
+    const size_t nb_n = (size_t)x.n_bands * n_all;
+    const size_t s_n = (size_t)x.C * x.K;
+    int K = x.K, nb = x.n_bands;
+    double dt = x.dt;
     Batch a;
-    a.f = h.f;
     a.B = 1;
-    a.H = H;
-    a.W = W;
-    a.C = C;
-    a.iters = inner_iters;
+    a.H = x.H;
+    a.W = x.W;
+    a.C = x.C;
+    a.iters = x.inner_iters;
     a.dt = &dt;
     a.K = &K;
-    a.edges = band_edges;
-    a.nb = &n_bands;
-    a.bands = h.bands;
-    a.S = h.S;
-    a.res = h.res;
-    a.stats = h.stats;
-    a.tau = TVSPEC_DEFAULT_TAU;
-    a.warm = 0;
-    a.ipl = 0;
-    a.precision = TVSPEC_DEFAULT_PRECISION;
-    a.st = h.stream;
+    a.edges = x.band_edges;
+    a.nb = &nb;
+    a.tau = tau;
+    a.warm = o.warm_start;
+    a.ipl = o.iters_per_launch;
+    a.precision = o.precision;
+    a.solver = solver;
+    a.sigma = solver == kSolverPDHG ? sigma : 0.0;
+    HostIO &h = g_hostio[dev];
+    if (o.device_ptrs) {
+        a.f = x.f;
+        a.bands = x.bands;
+        a.S = x.S;
+        a.res = x.residual;
+        a.stats = x.stats;
+        a.st = (hipStream_t)o.stream;
+    } else {
+        if (!h.stream)
+            HIP_TRY(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+        TVSPEC_TRY(grow(h.f, h.f_n, n_all));
+        TVSPEC_TRY(grow(h.bands, h.bands_n, nb_n));
+        TVSPEC_TRY(grow(h.S, h.s_n, s_n));
+        TVSPEC_TRY(grow(h.res, h.r_n, n_all));
+        if (!h.stats)
+            HIP_TRY(hipMalloc((void **)&h.stats, TVSPEC_NSTATS * sizeof(double)));
+        a.f = h.f;
+        a.bands = h.bands;
+        a.S = h.S;
+        a.res = h.res;
+        a.stats = h.stats;
+        a.st = h.stream;
+        HIP_TRY(hipMemcpyAsync(h.f, x.f, n_all * sizeof(float), hipMemcpyHostToDevice, a.st));
+    }
+    CallEvents ev;
+    if (rep) {
+        HIP_TRY(hipEventCreate(&ev.e0));
+        HIP_TRY(hipEventCreate(&ev.e1));
+        HIP_TRY(hipEventRecord(ev.e0, a.st));
+    }
     TVSPEC_TRY(run_batch(a));
-    HIP_TRY(hipMemcpyAsync(bands, h.bands, nb_n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
-    HIP_TRY(hipMemcpyAsync(S, h.S, s_n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
-    HIP_TRY(hipMemcpyAsync(residual, h.res, n_all * sizeof(double), hipMemcpyDeviceToHost, h.stream));
-    HIP_TRY(hipStreamSynchronize(h.stream));
+    if (rep)
+        HIP_TRY(hipEventRecord(ev.e1, a.st));
+    double st_h[TVSPEC_NSTATS] = {0.0, 0.0, 0.0, 0.0};
+    if (!o.device_ptrs) {
+        HIP_TRY(hipMemcpyAsync(x.bands, h.bands, nb_n * sizeof(double), hipMemcpyDeviceToHost, a.st));
+        HIP_TRY(hipMemcpyAsync(x.S, h.S, s_n * sizeof(double), hipMemcpyDeviceToHost, a.st));
+        HIP_TRY(hipMemcpyAsync(x.residual, h.res, n_all * sizeof(double), hipMemcpyDeviceToHost, a.st));
+    }
+    if (rep || !o.device_ptrs) {
+        if (rep || x.stats)
+            HIP_TRY(hipMemcpyAsync(st_h, a.stats, sizeof(st_h), hipMemcpyDeviceToHost, a.st));
+        HIP_TRY(hipStreamSynchronize(a.st));
+        if (!o.device_ptrs && x.stats)
+            std::memcpy(x.stats, st_h, sizeof(st_h));
+    }
+    if (rep) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        rep->recon_err = st_h[0];
+        rep->mean_err = st_h[1];
+        rep->nonfinite = st_h[2];
+        rep->device_ms = (double)ms;
+        rep->total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (st_h[2] > 0.0)
+            return fail(TVSPEC_ENUMERIC, "input holds a NaN or infinity (outputs are meaningless)");
+    }
     return TVSPEC_OK;
+}
+
+extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, int K, int inner_iters,
+                                const int *band_edges, int n_bands, double *bands, double *S, double *residual)
+{
+    tvspec_args x;
+    x.f = f;
+    x.H = H;
+    x.W = W;
+    x.C = C;
+    x.dt = dt;
+    x.K = K;
+    x.inner_iters = inner_iters;
+    x.band_edges = band_edges;
+    x.n_bands = n_bands;
+    x.bands = bands;
+    x.S = S;
+    x.residual = residual;
+    x.stats = nullptr;
+    return tvspec_decompose_ex(&x, nullptr, nullptr);
 }
 
 extern "C" int tvspec_dyadic_edges(int K, int n_bands, int *edges)
@@ -498,7 +653,9 @@ extern "C" void tvspec_release(void)
         (void)hipDeviceSynchronize();
         for (int m = 0; m < kModes; ++m) {
             free_dev(g_arena[d][m].base);
-            g_arena[d][m].bytes = 0;
+            if (g_arena[d][m].done)
+                (void)hipEventDestroy(g_arena[d][m].done);
+            g_arena[d][m] = Arena();
         }
         HostIO &h = g_hostio[d];
         free_dev(h.f);

@@ -40,6 +40,8 @@ EXPORTS = (
     "tvspec_decompose_dev",
     "tvspec_decompose_batch_dev",
     "tvspec_decompose_pdhg_dev",
+    "tvspec_decompose_ex",
+    "tvspec_default_options",
     "tvspec_dyadic_edges",
     "tvspec_timing_enable",
     "tvspec_timing_read",
@@ -75,6 +77,30 @@ class _ServerStats(ctypes.Structure):
                 ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
 
+class _Args(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int), ("C", ctypes.c_int),
+                ("dt", ctypes.c_double), ("K", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("band_edges", ctypes.c_void_p), ("n_bands", ctypes.c_int),
+                ("bands", ctypes.c_void_p), ("S", ctypes.c_void_p), ("residual", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("warm_start", ctypes.c_int), ("precision", ctypes.c_int), ("iters_per_launch", ctypes.c_int),
+                ("device_ptrs", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("recon_err", ctypes.c_double), ("mean_err", ctypes.c_double), ("nonfinite", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+TVSPEC_SOLVER_CHAMBOLLE = 0
+TVSPEC_SOLVER_PDHG = 1
+SOLVERS = {"chambolle": TVSPEC_SOLVER_CHAMBOLLE, "pdhg": TVSPEC_SOLVER_PDHG}
+
+
 class TvspecError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("tvspec error %d: %s" % (code, msg))
@@ -95,6 +121,10 @@ def _load():
     lib.tvspec_decompose_batch_dev.restype = i
     lib.tvspec_decompose_pdhg_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, d, i, i, i, vp]
     lib.tvspec_decompose_pdhg_dev.restype = i
+    lib.tvspec_decompose_ex.argtypes = [ctypes.POINTER(_Args), ctypes.POINTER(_Options), ctypes.POINTER(_Report)]
+    lib.tvspec_decompose_ex.restype = i
+    lib.tvspec_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.tvspec_default_options.restype = None
     lib.tvspec_dyadic_edges.argtypes = [i, i, vp]
     lib.tvspec_dyadic_edges.restype = i
     lib.tvspec_timing_enable.argtypes = [i]
@@ -265,6 +295,76 @@ def tvspec_decompose_pdhg_dev(f: torch.Tensor, dt: float, K: int, inner_iters: i
             out["stats"].data_ptr(), float(tau), float(sigma), 1 if warm_start else 0,
             PRECISIONS[precision], int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
     return out
+
+
+def tvspec_default_options() -> dict:
+    """The options tvspec_decompose_ex uses when given none."""
+    o = _Options()
+    _lib.tvspec_default_options(ctypes.byref(o))
+    return {k: getattr(o, k) for k, _ in _Options._fields_}
+
+
+def tvspec_decompose_ex(f, dt: float, K: int, inner_iters: int, band_edges, solver: str = "chambolle",
+                        tau: float = 0.0, sigma: float = 0.0, warm_start: bool = False,
+                        precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
+                        stream: torch.cuda.Stream | None = None, report: bool = True, out: dict | None = None):
+    """tvspec_decompose_ex: f is a (C,H,W)/(H,W) float32 numpy array (host
+    buffers, synchronous) or GPU tensor (device buffers on `stream`).
+
+    Returns (outputs, report): outputs as tvspec_decompose (numpy) or
+    tvspec_decompose_dev (tensors, with stats); report a dict of recon_err,
+    mean_err, nonfinite, device_ms, total_ms, or None with report=False."""
+    e = _edges_array(band_edges)
+    B = e.size - 1
+    o = _Options()
+    _lib.tvspec_default_options(ctypes.byref(o))
+    o.solver = SOLVERS[solver]
+    o.tau = float(tau)
+    o.sigma = float(sigma)
+    o.warm_start = 1 if warm_start else 0
+    o.precision = PRECISIONS[precision]
+    o.iters_per_launch = int(iters_per_launch)
+    if isinstance(f, torch.Tensor):
+        if not f.is_cuda or f.dtype != torch.float32:
+            raise TypeError("a tensor f must be a float32 GPU tensor")
+        if f.dim() == 2:
+            f = f.unsqueeze(0)
+        if f.dim() != 3:
+            raise ValueError("f must be (C,H,W) or (H,W)")
+        f = f.contiguous()
+        C, H, W = f.shape
+        dev = f.device
+        outs = _outputs(out, B, C, H, W, int(K), dev)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        o.device_ptrs = 1
+        o.stream = st.cuda_stream
+        args = _Args(f.data_ptr(), H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
+                     outs["bands"].data_ptr(), outs["S"].data_ptr(), outs["residual"].data_ptr(),
+                     outs["stats"].data_ptr())
+    else:
+        f = np.asarray(f)
+        if f.ndim == 2:
+            f = f[None]
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        C, H, W = f.shape
+        outs = {"bands": np.empty((B, C, H, W), dtype=np.float64), "S": np.empty((C, K), dtype=np.float64),
+                "residual": np.empty((C, H, W), dtype=np.float64),
+                "stats": np.empty((TVSPEC_NSTATS,), dtype=np.float64)}
+        o.device_ptrs = 0
+        args = _Args(f.ctypes.data, H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
+                     outs["bands"].ctypes.data, outs["S"].ctypes.data, outs["residual"].ctypes.data,
+                     outs["stats"].ctypes.data)
+        dev = None
+    rep = _Report() if report else None
+    if dev is not None:
+        with torch.cuda.device(dev):
+            rc = _lib.tvspec_decompose_ex(ctypes.byref(args), ctypes.byref(o),
+                                          ctypes.byref(rep) if rep is not None else None)
+    else:
+        rc = _lib.tvspec_decompose_ex(ctypes.byref(args), ctypes.byref(o),
+                                      ctypes.byref(rep) if rep is not None else None)
+    _check(rc)
+    return outs, ({k: getattr(rep, k) for k, _ in _Report._fields_} if rep is not None else None)
 
 
 def tvspec_decompose_batch_dev(f: torch.Tensor, dt, K, inner_iters: int, band_edges,

@@ -212,11 +212,62 @@ def test_server_structs_match_header(tv):
     """The binding's ctypes structures have the header's field order."""
     text = open(HEADER).read()
     for name, cls in (("tvspec_request", tv._Request), ("tvspec_result", tv._Result),
-                      ("tvspec_server_stats", tv._ServerStats)):
+                      ("tvspec_server_stats", tv._ServerStats), ("tvspec_args", tv._Args),
+                      ("tvspec_options", tv._Options), ("tvspec_report", tv._Report)):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"[\s\*]([A-Za-z_][A-Za-z_0-9]*)\s*(?=[,;])", body)
         assert fields == [f for f, _ in cls._fields_], (name, fields)
+
+
+def test_ex_default_options(tv):
+    o = tv.tvspec_default_options()
+    assert o["solver"] == tv.TVSPEC_SOLVER_CHAMBOLLE and o["tau"] == 0.0 and o["warm_start"] == 0
+    assert o["precision"] == tv.TVSPEC_PRECISION_MIXED and o["device_ptrs"] == 0 and o["stream"] is None
+
+
+EX_BAD = [
+    (dict(solver=2), "solver"), (dict(device_ptrs=2), "device_ptrs"), (dict(tau=0.3), "tau"),
+    (dict(solver=1, tau=0.5, sigma=0.5), "PDHG"), (dict(precision=4), "precision"),
+    (dict(iters_per_launch=9), "iters_per_launch"), (dict(H=1), "H and W"), (dict(K=0), "K"),
+    (dict(device_ptrs=1, stats=None), "null"), (dict(f=None), "null"),
+]
+
+
+@pytest.mark.parametrize("bad,msg", EX_BAD)
+def test_ex_entry_validation_without_a_device(tv, bad, msg):
+    """tvspec_decompose_ex rejects bad arguments and options with
+    TVSPEC_EINVAL before any device work (host buffers stand in for device
+    ones; none is touched)."""
+    lib = ctypes.CDLL(LIB)
+    lib.tvspec_decompose_ex.argtypes = [ctypes.POINTER(tv._Args), ctypes.POINTER(tv._Options),
+                                        ctypes.POINTER(tv._Report)]
+    lib.tvspec_last_error.restype = ctypes.c_char_p
+    buf = np.zeros(256, np.float64)
+    e = np.array([0, 1, 4], dtype=np.int32)
+    a = dict(f=buf.ctypes.data, H=4, W=5, C=1, dt=0.1, K=4, iters=3, stats=buf.ctypes.data)
+    o = tv._Options()
+    lib_o = ctypes.CDLL(LIB)
+    lib_o.tvspec_default_options(ctypes.byref(o))
+    for k, v in bad.items():
+        if k in a:
+            a[k] = v
+        else:
+            setattr(o, k, v)
+    args = tv._Args(a["f"], a["H"], a["W"], a["C"], a["dt"], a["K"], a["iters"], e.ctypes.data, 2,
+                    buf.ctypes.data, buf.ctypes.data, buf.ctypes.data, a["stats"])
+    rep = tv._Report()
+    assert lib.tvspec_decompose_ex(ctypes.byref(args), ctypes.byref(o), ctypes.byref(rep)) == -1
+    assert msg in lib.tvspec_last_error().decode()
+    assert lib.tvspec_decompose_ex(None, None, None) == -1
+
+
+def test_ex_host_nonfinite_before_device_work(tv):
+    f = np.zeros((3, 4), np.float32)
+    f[2, 1] = np.nan
+    with pytest.raises(tv.TvspecError) as ei:
+        tv.tvspec_decompose_ex(f, 0.1, 2, 3, [0, 2])
+    assert ei.value.code == tv.TVSPEC_ENUMERIC
 
 
 def test_product_path_never_reaches_the_oracle():
