@@ -233,6 +233,33 @@ TVSPEC_API int tvspec_decompose_dev(const float *f, int H, int W, int C, double 
                          int precision, int iters_per_launch, void *stream);
 
 /*
+ * Allocation-free variant of tvspec_decompose_dev, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (bit for bit),
+ * layouts, ownership, ordering and errors as tvspec_decompose_dev.  The call
+ * allocates nothing (no hipMalloc, no pinned staging, no memset: one setup
+ * kernel writes the slot table from arguments passed by value); its scratch
+ * is a fixed 64 MiB device array inside the library, one per device, held
+ * until the process ends.
+ *
+ * Limits: the decomposition's scratch must fit in 64 MiB, about
+ * C*H*W*(2*4*s + 2*g + 24) + 8*C*K*ceil(H*W/256) bytes + 4*K (s, g as for the
+ * server's working state: 512x512x1 at K = 200 in MIXED needs ~18 MB,
+ * 1024x1024x1 does not fit), and n_bands <= 64; larger calls return
+ * TVSPEC_EINVAL with the size in the message, before any device work.
+ *
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (everything a call reads is written by the call first):
+ * calls that overlap on one device -- different streams or threads --
+ * race.  Serialise them.  Calls of the other entry points do not share it.
+ */
+TVSPEC_API int tvspec_decompose_noalloc_dev(const float *f, int H, int W, int C, double dt, int K,
+                                            int inner_iters, const int *band_edges, int n_bands,
+                                            double *bands, double *S, double *residual, double *stats,
+                                            double tau, int warm_start, int precision,
+                                            int iters_per_launch, void *stream);
+
+/*
  * Device entry point with the primal-dual ROF solver in place of Chambolle's
  * dual fixed point: every implicit Euler step (Sec. 2.2, Eq. (8)) is solved by
  * inner_iters iterations of Chambolle and Pock's first-order primal-dual

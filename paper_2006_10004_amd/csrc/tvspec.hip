@@ -20,6 +20,16 @@
 
 #define TVSPEC_VERSION_STRING "tvspec 0.3.0 (gfx950)"
 
+// Scratch of the allocation-free entry point (tvspec_decompose_noalloc_dev):
+// slot table | band rows | non-finite counter | slot buffers, carved as the
+// arena of the other entry points.  Every device the library runs on holds
+// its own copy until the process ends.  Host code never takes this name as
+// an address: the device address of each copy is looked up once per device
+// (noalloc_scratch below) and passed to the kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxBands = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace tvspec {
 namespace {
 
@@ -155,6 +165,49 @@ struct Batch {
     int solver = kSolverChambolle;
     double sigma = 0.0;
 };
+
+// The slot descriptor and band edges of an allocation-free call, passed by
+// value (no host staging, nothing to capture but a kernel launch).
+struct NoAllocSetup {
+    SlotDesc slot;
+    int edges[kNoAllocMaxBands + 1];
+};
+
+// Writes the slot table entry, the band row of every sample k = 0..K
+// (sample k belongs to band j when e_j < k <= e_{j+1}; sample 0 carries no
+// phi) and clears the non-finite counter.  One block.
+__global__ __launch_bounds__(256) void k_noalloc_setup(NoAllocSetup a, SlotDesc *table, int *rows,
+                                                       unsigned int *nf)
+{
+    for (int k = threadIdx.x; k <= a.slot.K; k += blockDim.x) {
+        int r = 0;
+        for (int j = 0; j < a.slot.nbands; ++j)
+            if (k > a.edges[j] && k <= a.edges[j + 1])
+                r = j;
+        rows[k] = r;
+    }
+    if (threadIdx.x == 0) {
+        *table = a.slot;
+        *nf = 0u;
+    }
+}
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call on the device, with that device current).
+char *g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(int dev, char **out)
+{
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr)
+            return fail(TVSPEC_EDEVICE, "no device address for the allocation-free scratch");
+        g_noalloc_ptr[dev] = (char *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return TVSPEC_OK;
+}
 
 int run_batch(const Batch &a)
 {
@@ -595,6 +648,69 @@ extern "C" int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
     x.residual = residual;
     x.stats = nullptr;
     return tvspec_decompose_ex(&x, nullptr, nullptr);
+}
+
+extern "C" int tvspec_decompose_noalloc_dev(const float *f, int H, int W, int C, double dt, int K,
+                                            int inner_iters, const int *band_edges, int n_bands, double *bands,
+                                            double *S, double *residual, double *stats, double tau,
+                                            int warm_start, int precision, int iters_per_launch, void *stream)
+{
+    g_last_error.clear();
+    if (!f || !band_edges || !bands || !S || !residual || !stats)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    TVSPEC_TRY(validate_shape(1, H, W, C, inner_iters));
+    TVSPEC_TRY(validate_image(dt, K, band_edges, n_bands));
+    TVSPEC_TRY(validate_opts(tau, warm_start, precision, iters_per_launch));
+    if (n_bands > kNoAllocMaxBands)
+        return fail(TVSPEC_EINVAL, "the allocation-free entry point takes at most 64 bands");
+    const size_t table_bytes = align256(sizeof(SlotDesc));
+    const size_t rows_bytes = align256(((size_t)K + 1) * sizeof(int));
+    const size_t nf_bytes = align256(sizeof(unsigned int));
+    const size_t need = table_bytes + rows_bytes + nf_bytes +
+                        slot_scratch_bytes(precision, kSolverChambolle, H, W, C, K);
+    if (need > kNoAllocScratchBytes)
+        return fail(TVSPEC_EINVAL, "the decomposition needs " + std::to_string(need) +
+                                       " bytes of scratch; the allocation-free entry point has " +
+                                       std::to_string(kNoAllocScratchBytes));
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(TVSPEC_EDEVICE, "device index out of range");
+    char *base = nullptr;
+    TVSPEC_TRY(noalloc_scratch(dev, &base));
+    SlotDesc *d_table = (SlotDesc *)base;
+    int *d_rows = (int *)(base + table_bytes);
+    unsigned int *d_nf = (unsigned int *)(base + table_bytes + rows_bytes);
+    char *slot_base = base + table_bytes + rows_bytes + nf_bytes;
+
+    NoAllocSetup su;
+    std::memset(&su, 0, sizeof(su));
+    SlotDesc &d = su.slot;
+    slot_carve(d, slot_base, precision, kSolverChambolle, H, W, C, K);
+    d.band_rows = d_rows;
+    d.nonfinite = d_nf;
+    d.f = f;
+    d.bands = bands;
+    d.S = S;
+    d.res = residual;
+    d.stats = stats;
+    d.dt = dt;
+    d.nbands = n_bands;
+    for (int j = 0; j <= n_bands; ++j)
+        su.edges[j] = band_edges[j];
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(256), 0, st, su, d_table, d_rows, d_nf);
+    HIP_TRY(hipGetLastError());
+
+    StepConfig cfg{H, W, C, inner_iters, tau, warm_start, iters_per_launch, precision};
+    cfg.timed = 0;
+    TVSPEC_TRY(engine_init(cfg, d_table, 0, 1, st));
+    int parity = 0;
+    for (int s = 0; s <= K; ++s)
+        TVSPEC_TRY(engine_step(cfg, d_table, 1, &parity, st, C));
+    return engine_finalize(cfg, d_table, 0, 1, K, st);
 }
 
 extern "C" int tvspec_dyadic_edges(int K, int n_bands, int *edges)

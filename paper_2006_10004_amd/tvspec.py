@@ -41,6 +41,7 @@ EXPORTS = (
     "tvspec_decompose_batch_dev",
     "tvspec_decompose_pdhg_dev",
     "tvspec_decompose_ex",
+    "tvspec_decompose_noalloc_dev",
     "tvspec_default_options",
     "tvspec_dyadic_edges",
     "tvspec_timing_enable",
@@ -121,6 +122,8 @@ def _load():
     lib.tvspec_decompose_batch_dev.restype = i
     lib.tvspec_decompose_pdhg_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, d, i, i, i, vp]
     lib.tvspec_decompose_pdhg_dev.restype = i
+    lib.tvspec_decompose_noalloc_dev.argtypes = [vp, i, i, i, d, i, i, vp, i, vp, vp, vp, vp, d, i, i, i, vp]
+    lib.tvspec_decompose_noalloc_dev.restype = i
     lib.tvspec_decompose_ex.argtypes = [ctypes.POINTER(_Args), ctypes.POINTER(_Options), ctypes.POINTER(_Report)]
     lib.tvspec_decompose_ex.restype = i
     lib.tvspec_default_options.argtypes = [ctypes.POINTER(_Options)]
@@ -265,6 +268,37 @@ def tvspec_decompose_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, b
             f.data_ptr(), H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
             out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
             out["stats"].data_ptr(), float(tau), 1 if warm_start else 0, prec,
+            int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def tvspec_decompose_noalloc_dev(f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges, out: dict,
+                                 tau: float = TVSPEC_DEFAULT_TAU, warm_start: bool = False,
+                                 precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
+                                 stream: torch.cuda.Stream | None = None):
+    """Allocation-free variant of tvspec_decompose_dev: the library uses its
+    fixed per-device scratch array and allocates nothing.  `out` must pass
+    preallocated output tensors (bands (B,C,H,W), S (C,K), residual (C,H,W),
+    stats (4,) float64 on f's device); they are returned."""
+    if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float32:
+        raise TypeError("f must be a float32 GPU tensor")
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    if f.dim() != 3 or not f.is_contiguous():
+        raise ValueError("f must be a contiguous (C,H,W) or (H,W) tensor")
+    if out is None:
+        raise ValueError("the allocation-free entry point needs preallocated outputs")
+    C, H, W = f.shape
+    e = _edges_array(band_edges)
+    B = e.size - 1
+    dev = f.device
+    out = _outputs(out, B, C, H, W, int(K), dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        _check(_lib.tvspec_decompose_noalloc_dev(
+            f.data_ptr(), H, W, C, float(dt), int(K), int(inner_iters), e.ctypes.data, B,
+            out["bands"].data_ptr(), out["S"].data_ptr(), out["residual"].data_ptr(),
+            out["stats"].data_ptr(), float(tau), 1 if warm_start else 0, PRECISIONS[precision],
             int(iters_per_launch), ctypes.c_void_p(st.cuda_stream)))
     return out
 

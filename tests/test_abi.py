@@ -270,6 +270,26 @@ def test_ex_host_nonfinite_before_device_work(tv):
     assert ei.value.code == tv.TVSPEC_ENUMERIC
 
 
+def test_noalloc_entry_rejects_oversize_without_a_device():
+    """The allocation-free entry point checks its scratch need against its
+    fixed array before any device work (host buffers stand in for device
+    ones; none is touched)."""
+    lib = ctypes.CDLL(LIB)
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.tvspec_decompose_noalloc_dev.argtypes = [vp, ci, ci, ci, cd, ci, ci, vp, ci, vp, vp, vp, vp, cd, ci, ci,
+                                                 ci, vp]
+    lib.tvspec_last_error.restype = ctypes.c_char_p
+    e = np.array([0, 4], dtype=np.int32)
+    fake = vp(0x1000)
+    rc = lib.tvspec_decompose_noalloc_dev(fake, 1024, 1024, 3, 0.01, 4, 5, e.ctypes.data_as(vp), 1, fake, fake,
+                                          fake, fake, 0.248, 0, 2, 0, None)
+    assert rc == -1 and b"bytes of scratch" in lib.tvspec_last_error()
+    many = np.arange(66, dtype=np.int32)
+    rc = lib.tvspec_decompose_noalloc_dev(fake, 8, 8, 1, 0.01, 65, 5, many.ctypes.data_as(vp), 65, fake, fake,
+                                          fake, fake, 0.248, 0, 2, 0, None)
+    assert rc == -1 and b"64 bands" in lib.tvspec_last_error()
+
+
 def test_product_path_never_reaches_the_oracle():
     """No module of the package, nor the HIP source, imports or links the
     oracle; there is no CPU fallback."""
