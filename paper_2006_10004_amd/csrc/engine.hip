@@ -102,24 +102,25 @@ __device__ __forceinline__ void chambolle_update(S &px, S &py, S ax, S ay, S tau
         px = A::fma_(tau, ax, px) * r;
         py = A::fma_(tau, ay, py) * r;
     } else {
-        // float64 update in increment form, p += tau (a - |a| p) / (1 + tau |a|),
-        // with |a| and the reciprocal from the float32 hardware estimates
-        // (v_rsq_f32, v_rcp_f32) refined by one Newton step in float64
-        // (relative error ~1e-14; the float64 square root and division
-        // sequences cost several times more).  Below |a| = 1e-15 the
-        // estimate's argument would leave the float32 normal range, and |a| is
-        // taken as 0: the increment then differs by at most tau |a| |p|, far
-        // below the rounding of p.
+        // float64 update with |a| and the reciprocal from the float32
+        // hardware estimates (v_rsq_f32, v_rcp_f32), each refined by one
+        // float64 Newton step (relative error ~1e-14; the float64 square
+        // root and division sequences cost several times more):
+        //     y ~ 1/sqrt(x),  s = x y,  |a| = s + s (1 - s y) / 2
+        //     r ~ 1/den,      r' = r + r (1 - den r)
+        // The estimate's argument is clamped to 1e-30 so that it stays a
+        // normal float32; below that |a| comes out as ~1.5e15 x <= 1.5e-15
+        // instead of sqrt(x) <= 1e-15, which moves 1 + tau |a| by less
+        // than its rounding.
         const S x = ax * ax + ay * ay;
-        S y = (S)__builtin_amdgcn_rsqf((float)x);
-        y = __builtin_fma(S(0.5) * y, __builtin_fma(-(x * y), y, S(1)), y);
-        const S nrm = x > S(1e-30) ? x * y : S(0);
+        const S y = (S)__builtin_amdgcn_rsqf(fmaxf((float)x, 1e-30f));
+        const S sx = x * y;
+        const S nrm = __builtin_fma(sx, __builtin_fma(-sx, S(0.5) * y, S(0.5)), sx);
         const S den = __builtin_fma(tau, nrm, S(1));
-        S r = (S)__builtin_amdgcn_rcpf((float)den);
-        r = __builtin_fma(r, __builtin_fma(-den, r, S(1)), r);
-        const S tr = tau * r;
-        px += tr * __builtin_fma(-nrm, px, ax);
-        py += tr * __builtin_fma(-nrm, py, ay);
+        const S r0 = (S)__builtin_amdgcn_rcpf((float)den);
+        const S r = __builtin_fma(r0, __builtin_fma(-den, r0, S(1)), r0);
+        px = __builtin_fma(tau, ax, px) * r;
+        py = __builtin_fma(tau, ay, py) * r;
     }
 }
 

@@ -36,8 +36,28 @@ def test_primal_dual_traffic_record():
     assert rec["write_kib_per_dispatch"] == 4 * 512 * 512 * 8 / 1024
     want = (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * rec["write_scale"]) * 1024
     assert abs(rec["traffic_bytes_per_launch"] - want) < 1024
-    assert bench.measured_traffic("mixed", 0, bench.PDHG_TRAFFIC_RECORD) == rec["traffic_bytes_per_launch"]
+    import hashlib
+    sha = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
+    expect = rec["traffic_bytes_per_launch"] if rec["source_sha256"] == sha else None
+    assert bench.measured_traffic("mixed", 0, bench.PDHG_TRAFFIC_RECORD) == expect
     assert bench.measured_traffic("f32", 0, bench.PDHG_TRAFFIC_RECORD) is None
+
+
+def test_alu_roofline_record():
+    """The roofline of a blocked tile kernel: algorithmic flops per launch
+    over the average launch, against the mode's vector peak; the HBM rate
+    only from counter bytes, and null without them."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = {"kernel_ms": 10.0, "launches": 1000, "pixel_iters": 1000 * 2_000_000}
+    r = bench.alu_roofline("k", t, 20.0, "mixed", 18, 40, None)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert abs(r["achieved"] - 18 * 2e6 / 10e-6 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12
+    assert r["traffic"] is None and r["hbm_GBps"] is None
+    assert abs(r["effective_GBps"] - 40 * 2e6 / 10e-6 / 1e9) < 1e-6
+    r = bench.alu_roofline("k", t, 20.0, "f32", 18, 24, 10_000_000)
+    assert r["peak"] == 157.3 and abs(r["hbm_GBps"] - 1000.0) < 1e-9
 
 
 def test_cpu_baseline_reports_all_threads_and_one_thread():

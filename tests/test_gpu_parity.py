@@ -320,6 +320,25 @@ def test_megapixel_flow_full_size(tv, orc, side):
     assert torch.equal(gt["residual"], g["residual"].transpose(1, 2))
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_megapixel_flow_full_length_against_oracle(tv, orc):
+    """The megapixel fallback flow over its full length: 3 x 1024 x 1024,
+    300 shapes, dt 0.002, K = 300 flow steps of 200 iterations, 4 dyadic
+    bands, through the batched entry point the benchmark times, against the
+    oracle's full run (every sample, every pixel, every channel).  The long
+    flow weights step differences by up to k = 300 in phi, where precision
+    errors of the inner iteration grow most."""
+    f = synth.shapes_image(synth.megapixel_spec(1024), 71024)
+    ft = torch.from_numpy(f).to("cuda:0")
+    K, edges = 300, [0, 1, 2, 4, 300]
+    print("megapixel full-length flow: 3x1024x1024, K 300, 200 iterations", flush=True)
+    g = batch_one(tv, ft, MEGA_FLOW["dt"], K, MEGA_FLOW["iters"], edges)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    r = orc.decompose(f, MEGA_FLOW["dt"], K, MEGA_FLOW["iters"], edges)
+    check_parity(g, r)
+
+
 def test_batch_equals_separate_calls(tv, orc):
     """One batched launch sequence over images with different dt, K and band
     edges gives each image's single-call result bit for bit, and matches the

@@ -263,6 +263,31 @@ def test_server_against_oracle(tv, orc):
     assert st[0] <= 1e-12 and st[2] == 0
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_serving_size_request_against_oracle(tv, orc):
+    """One request of the serving workload's largest size (3 x 1024 x 1024,
+    40 shapes, dt 0.005, K 100, 150 iterations, 4 dyadic bands) through the
+    server, sharing it with a smaller request, against the oracle's full
+    run."""
+    dev = torch.device("cuda:0")
+    f = synth.shapes_image(synth.serving_spec(1024), 4242)
+    small = torch.from_numpy(image(3, 128, 128, 4243)).to(dev)
+    edges = [0, 1, 2, 4, 100]
+    print("serving-size request: 3x1024x1024, K 100, 150 iterations", flush=True)
+    with tv.Server(4 << 30) as srv:
+        t, o = srv.submit(torch.from_numpy(f).to(dev), 0.005, 100, 150, edges)
+        t2, _ = srv.submit(small, 0.005, 100, 150, edges)
+        wait_all(srv, [t, t2])
+    ref = orc.decompose(f, dt=0.005, K=100, iters=150, edges=edges)
+    assert np.abs(o["bands"].cpu().numpy() - ref["bands"]).max() <= TOL_BANDS
+    assert np.abs(o["residual"].cpu().numpy() - ref["residual"]).max() <= TOL_BANDS
+    S = o["S"].cpu().numpy()
+    assert np.abs(S - ref["S"]).max() / np.abs(ref["S"]).max() <= TOL_S64
+    st = o["stats"].cpu().numpy()
+    assert st[0] <= 1e-12 and st[1] <= 1e-12 and st[2] == 0
+
+
 def test_invalid_requests(tv):
     from paper_2006_10004_amd import tvspec
     dev = torch.device("cuda:0")
