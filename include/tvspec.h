@@ -79,7 +79,7 @@ extern "C" {
  *   F64    IEEE float64 dual field and arithmetic
  *   MIXED  float64 dual field and arithmetic; |grad w| and the reciprocal
  *          from float32 hardware estimates refined by one float64 Newton
- *          step; grad(g)/dt stored in float32.  Float64-level results
+ *          step.  Float64-level results
  *          (~3e-6 on the workload above) at less cost than F64.  Default. */
 #define TVSPEC_PRECISION_F32 0
 #define TVSPEC_PRECISION_F64 1
@@ -244,7 +244,7 @@ TVSPEC_API int tvspec_decompose_dev(const float *f, int H, int W, int C, double 
  *
  * Limits: the decomposition's scratch must fit in 64 MiB, about
  * C*H*W*(2*4*s + 2*g + 24) + 8*C*K*ceil(H*W/256) bytes + 4*K (s, g as for the
- * server's working state: 512x512x1 at K = 200 in MIXED needs ~18 MB,
+ * server's working state: 512x512x1 at K = 200 in MIXED needs ~16 MB,
  * 1024x1024x1 does not fit), and n_bands <= 64; larger calls return
  * TVSPEC_EINVAL with the size in the message, before any device work.
  *
@@ -343,7 +343,8 @@ TVSPEC_API int tvspec_decompose_batch_dev(const float *f, int B, int H, int W, i
  * Working state per request (what admission charges against the budget):
  * about C*H*W*(2*4*s + 2*g + 24) bytes + C*K*8*ceil(H*W/256) for the
  * partial sums of S, with s = 4 (F32) or 8 bytes per dual-field element and
- * g = 4 (F32, MIXED) or 8 (F64) per stored data-term element.
+ * g = 4 (F32) or 0 (MIXED, F64: they read the data term from the flow state)
+ * per stored data-term element.
  *
  *   budget_bytes      size of the pool (allocated at creation)
  *   tau, warm_start, precision

@@ -25,7 +25,7 @@ constexpr int kSolverPDHG = 1;      // Chambolle-Pock primal-dual
 
 struct SlotDesc {
     void *px[2], *py[2];  // dual field, ping-pong (state type of the mode)
-    void *gx, *gy;        // Chambolle: G = grad(g)/dt (type M of the mode)
+    void *gx, *gy;        // F32 Chambolle: G = grad(g)/dt (float32); else unused
     void *x[2], *xb[2];   // PDHG: primal iterate and its extrapolation, ping-pong
     double *u[2];         // flow state; u_s lives in u[s % 2]
     double *dprev;        // D_{s-1}
@@ -46,7 +46,8 @@ struct SlotDesc {
 };
 
 // Inner-iteration precision modes (TVSPEC_PRECISION_*): bytes per element of
-// the dual field (state) and of the stored data term G.
+// the dual field (state) and of the stored data-term gradient G (F32 only; the
+// float64 modes read the data term from the flow state, 0 bytes).
 size_t state_elem(int precision);
 size_t g_elem(int precision);
 
@@ -85,7 +86,7 @@ struct StepConfig {
 // dual-field parity flips after a step when this is odd).
 int tile_launches_per_step(const StepConfig &cfg, int nslots);
 
-// u_0 = f, G = grad(f)/dt, p = 0, bands = 0, k_cur = 0, active = 1, for
+// u_0 = f, p = 0, bands = 0 (F32: G = grad(f)/dt), k_cur = 0, active = 1, for
 // slots [first, first + count) of the table.
 int engine_init(const StepConfig &cfg, SlotDesc *d_slots, int first, int count, hipStream_t st);
 

@@ -10,8 +10,9 @@
 //                      Eq. (7) and the residual of Eq. (5).
 //
 // Device work per slot (one C x H x W image, channels independent):
-//   k_init           u_0 = f (float64), G = grad(f)/dt for the first solve,
-//                    p = 0, bands = 0, count of non-finite inputs;
+//   k_init           u_0 = f (float64), p = 0, bands = 0, count of
+//                    non-finite inputs (F32: G = grad(f)/dt of the first
+//                    solve);
 //   k_chambolle_tile the hot loop.  Each launch runs `iters` (<= TB) Jacobi
 //                    iterations of Chambolle's fixed point on a 32x32 output
 //                    tile whose (32+2TB)^2 neighbourhood is staged once; the
@@ -33,13 +34,14 @@
 //                    bit-reproducible run to run).
 //
 // Precision modes of the inner iteration.  S is the type of the dual field
-// and of the update arithmetic, M the type G is stored in:
+// and of the update arithmetic; M selects how |a| and the reciprocal are
+// formed (and, in F32, the type of the stored data-term gradient G):
 //   F32    S = float,  M = float   (IEEE-rounded float32 except the
 //          hardware square root and reciprocal estimates)
 //   F64    S = double, M = double  (IEEE float64 throughout)
 //   MIXED  S = double, M = float.  float64 arithmetic, but |a| and the
 //          reciprocal come from the float32 hardware estimates refined by one
-//          float64 Newton step, and G is stored in float32.  On gfx950, with
+//          float64 Newton step.  On gfx950, with
 //          packed float32 math off, float64 add and fma issue at the float32
 //          rate; what makes float64 dear is its square root and division
 //          sequences, which this avoids.  Float32 is not enough for long
@@ -171,8 +173,8 @@ __device__ __forceinline__ double block_max256(double v, double *sh)
 // ---------------------------------------------------------------------------
 // kernels
 
-// u_0 = f, G = grad f / dt (Chambolle only), p = 0 (both buffers), bands =
-// 0, for slot first + blockIdx.y; counts non-finite inputs; starts the slot
+// u_0 = f, p = 0 (both buffers), bands = 0 (F32 Chambolle: G = grad f / dt),
+// for slot first + blockIdx.y; counts non-finite inputs; starts the slot
 // at step 0.  For PDHG p is its dual field y; its primal iterates are set at
 // the start of every solve.
 template <typename S, typename M, bool PD>
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
         if (!isfinite(v))
             atomicAdd(sd.nonfinite, 1u);
         u[q] = (double)v;
-        if constexpr (!PD) {
+        if constexpr (!PD && !std::is_same<S, double>::value) {
             gx[q] = (j < W - 1) ? (M)(((double)f[q + 1] - (double)v) / dt) : M(0);
             gy[q] = (i < H - 1) ? (M)(((double)f[q + W] - (double)v) / dt) : M(0);
         }
@@ -218,35 +220,33 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
 
 // Temporally blocked Chambolle iterations.
 //
-// Chambolle's step needs a = grad(div p - g/dt).  It is evaluated as
-//     a = grad(div p) - G,   G = grad(g)/dt,
-// with G formed in float64 from the float64 flow state and stored in type M.
-// This is the same quantity; the order matters in float32: g/dt is large
-// (|g| <= 1, dt ~ 1e-3) and differencing two rounded values of it would bury
-// the small gradients of flat regions, whereas G carries only the relative
-// rounding of the gradient itself.
+// Chambolle's step needs a = grad w with w = div p - g/dt, g = u_k the data
+// of the slot's current solve.  The float64 modes (S = double) form exactly
+// that: w = div p - u_k/dt per pixel (u_k read once per launch from the
+// float64 flow state; MIXED multiplies by the rounded 1/dt, F64 divides),
+// then a = (w_right - w, w_down - w).  w is ~u/dt (up to ~1e3), and its
+// float64 rounding (~1e-13) is far below what the bands see.  In float32
+// (S = float) that rounding would bury the small gradients of flat regions,
+// so F32 keeps the gradient form a = grad(div p) - G with G = grad(g)/dt
+// formed in float64 once per solve and stored as float32: the same
+// quantity, carrying only G's relative rounding.
 //
 // Grid: (number of BX x BY output tiles, slots * C); NT threads (1024 by
 // default, so that every SIMD of the CU has four waves to interleave: the
 // per-pixel chain of LDS reads, square root and reciprocal is long and a tile
 // holds few pixels).  The workgroup stages the (BX+2TB) x (BY+2TB) region
-// around its tile: the dual field and G of every region pixel live in
-// registers of the thread that owns the pixel for all `iters` iterations;
-// LDS only carries the values a neighbour needs.  The LDS planes carry a
-// one-pixel ring that is never written, so neighbour reads need no tests.
-// One iteration on every region pixel:
+// around its tile: the dual field and the data term of every region pixel
+// live in registers of the thread that owns the pixel for all `iters`
+// iterations; LDS only carries the values a neighbour needs.  The LDS planes
+// carry a one-pixel ring that is never written, so neighbour reads need no
+// tests.  One iteration on every region pixel, two barriers:
 //     d   = (px - px_left) + (py - py_up)                      (div p)
-//     a   = ((d_right - d) - Gx, (d_down - d) - Gy), zero on the last
-//           column / row and outside the image
+//     w   = d - u_k/dt                                         (float64 modes)
+//     a   = (w_right - w, w_down - w)  or  ((d_right - d) - Gx, (d_down - d) - Gy),
+//           zero on the last column / row and outside the image
 //     p  <- (p + tau a) / (1 + tau |a|)
-// Two forms of the iteration, with identical arithmetic per pixel:
-//   OB = false  two barriers per iteration: d goes through LDS (px of the
-//               left pixel and py of the upper one for d, then d of the right
-//               and lower pixels for a);
-//   OB = true   one barrier per iteration: the dual field is double-buffered
-//               in LDS and each pixel forms d_right and d_down itself from the
-//               previous iterate, with the operations (and their order) the
-//               right and lower pixels use for their own d.
+// w (or d) goes through LDS between the two halves: px of the left pixel
+// and py of the upper one for d, then w of the right and lower pixels for a.
 // Pixels outside the image start with p = 0 and a = 0, so they keep p = 0;
 // that realises the Neumann divergence (p_x = 0 on the last column and
 // p_y = 0 on the last row is preserved by the update because a_x, a_y vanish
@@ -255,9 +255,9 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
 // is read from buffer `cur` of the slot and written to buffer 1 - cur.
 // Channel planes of slots whose flow is complete (inactive) are skipped.
 // The new dual vector of a pixel depends on the previous iterate within one
-// pixel (either form), so a region pixel at distance e from the region edge
-// is exact while the iteration count is <= e: after iters <= TB iterations
-// the BX x BY centre is exact and is written.
+// pixel, so a region pixel at distance e from the region edge is exact while
+// the iteration count is <= e: after iters <= TB iterations the BX x BY
+// centre is exact and is written.
 //
 // The same cone says which rows are still needed: the update of iteration it
 // (0-based) reaches the centre only from rows lo .. RY - 1 - lo, with lo =
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotDesc *__restrict__ slots,
 // straight-line passes the compiler interleaves, and with one workgroup per
 // CU that interleaving hides more latency than the skipped rows save
 // (measured at TB = 8 with several pixel-to-thread assignments).
-template <typename S, typename M, int BX, int BY, int TB, int NT, bool OB>
+template <typename S, typename M, int BX, int BY, int TB, int NT>
 __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restrict__ slots, int cur, int H, int W,
                                                       int C, int ntx, int ntiles, S tau, int iters, int zero_in)
 {
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
     const SlotDesc &sd = slots[slot];
     if (!sd.active)
         return;
+    constexpr bool kW = std::is_same<S, double>::value; // w-form data term
     constexpr int RX = BX + 2 * TB;
     constexpr int RY = BY + 2 * TB;
     constexpr int RN = RX * RY;
@@ -286,19 +287,21 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
     constexpr int LN = LX * (RY + 2);
     constexpr int PPT = (RN + NT - 1) / NT;
     constexpr bool kSkip = PPT == 2;      // rows outside the cone are skipped
-    constexpr int NB = OB ? 2 : 1;        // dual-field LDS buffers
-    __shared__ S s_px[NB][LN];
-    __shared__ S s_py[NB][LN];
-    __shared__ S s_d[OB ? 1 : LN];
+    __shared__ S s_px[LN];
+    __shared__ S s_py[LN];
+    __shared__ S s_d[LN];
 
     const size_t plane = (size_t)H * (size_t)W;
     const size_t coff = (size_t)chan * plane;
     const S *__restrict__ pxi = (const S *)sd.px[cur] + coff;
     const S *__restrict__ pyi = (const S *)sd.py[cur] + coff;
+    const double *__restrict__ ui = sd.u[sd.k_cur & 1] + coff;
     const M *__restrict__ gxi = (const M *)sd.gx + coff;
     const M *__restrict__ gyi = (const M *)sd.gy + coff;
     S *__restrict__ pxo = (S *)sd.px[1 - cur] + coff;
     S *__restrict__ pyo = (S *)sd.py[1 - cur] + coff;
+    const double dt = sd.dt;
+    const double idt = 1.0 / dt;
 
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
     // so give XCD x the x-th contiguous run of row-major tiles.
@@ -320,16 +323,13 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
             li = (e - 2 * LX + 1) * LX;          // left column
         else
             li = (e - 2 * LX - RY + 1) * LX + LX - 1; // right column
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            s_px[k][li] = S(0);
-            s_py[k][li] = S(0);
-        }
-        if constexpr (!OB)
-            s_d[li] = S(0);
+        s_px[li] = S(0);
+        s_py[li] = S(0);
+        s_d[li] = S(0);
     }
 
-    S px[PPT], py[PPT], d[PPT], gx[PPT], gy[PPT];
+    // gq: u_k/dt (w-form) or Gx (gradient form); gy: Gy (gradient form only)
+    S px[PPT], py[PPT], d[PPT], gq[PPT], gy[PPT];
     int li[PPT];     // LDS index of the pixel
     int rr[PPT];     // region row of the pixel (RY + 1 for the idle lanes of the last pass)
     S mx[PPT];       // 1 where a_x is live (inside the image, not its last column), else 0
@@ -337,8 +337,7 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int idx = threadIdx.x + m * NT;
-        S vx = S(0), vy = S(0);
-        M vgx = M(0), vgy = M(0);
+        S vx = S(0), vy = S(0), vq = S(0), vgy = S(0);
         bool ax_live = false, ay_live = false;
         int l = 0;
         rr[m] = RY + 1;
@@ -355,87 +354,70 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
                     vx = pxi[q];
                     vy = pyi[q];
                 }
-                vgx = gxi[q];
-                vgy = gyi[q];
+                if constexpr (kW) {
+                    if constexpr (std::is_same<M, double>::value)
+                        vq = ui[q] / dt;
+                    else
+                        vq = ui[q] * idt;
+                } else {
+                    vq = (S)gxi[q];
+                    vgy = (S)gyi[q];
+                }
                 ax_live = gj < W - 1;
                 ay_live = gi < H - 1;
             }
-            s_px[0][l] = vx;
-            s_py[0][l] = vy;
+            s_px[l] = vx;
+            s_py[l] = vy;
         }
         li[m] = l;
         px[m] = vx;
         py[m] = vy;
-        gx[m] = (S)vgx;
-        gy[m] = (S)vgy;
+        gq[m] = vq;
+        gy[m] = vgy;
         d[m] = S(0);
         mx[m] = ax_live ? S(1) : S(0);
         my[m] = ay_live ? S(1) : S(0);
     }
     __syncthreads();
 
-    if constexpr (OB) {
-        for (int it = 0; it < iters; ++it) {
-            const S *__restrict__ qx = s_px[it & 1];
-            const S *__restrict__ qy = s_py[it & 1];
-            S *__restrict__ wx = s_px[(it & 1) ^ 1];
-            S *__restrict__ wy = s_py[(it & 1) ^ 1];
-            const int lo = TB - iters + it + 1;
-            const unsigned span = (unsigned)(RY - 1 - 2 * lo);
+    for (int it = 0; it < iters; ++it) {
+        const int lo = TB - iters + it + 1;
+        const unsigned span = (unsigned)(RY - 1 - 2 * lo);
 #pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                if (kSkip ? (unsigned)(rr[m] - lo) <= span : (m < PPT - 1 || threadIdx.x + m * NT < RN)) {
-                    const int l = li[m];
-                    // the previous iterate around the pixel: unconditional
-                    // LDS reads, boundary masks multiply
-                    const S pxl = qx[l - 1], pxr = qx[l + 1];
-                    const S pxd = qx[l + LX], pxdl = qx[l + LX - 1];
-                    const S pyu = qy[l - LX], pyur = qy[l - LX + 1];
-                    const S pyr = qy[l + 1], pyd = qy[l + LX];
-                    const S dv = (px[m] - pxl) + (py[m] - pyu);
-                    const S dr = (pxr - px[m]) + (pyr - pyur);
-                    const S dd = (pxd - pxdl) + (pyd - py[m]);
-                    const S ax = ((dr - dv) - gx[m]) * mx[m];
-                    const S ay = ((dd - dv) - gy[m]) * my[m];
-                    chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
-                    wx[l] = px[m];
-                    wy[l] = py[m];
-                }
+        for (int m = 0; m < PPT; ++m) {
+            if (kSkip ? (unsigned)(rr[m] - lo) <= span + 1u : (m < PPT - 1 || threadIdx.x + m * NT < RN)) {
+                const int l = li[m];
+                S dv = (px[m] - s_px[l - 1]) + (py[m] - s_py[l - LX]);
+                if constexpr (kW)
+                    dv = dv - gq[m];
+                d[m] = dv;
+                s_d[l] = dv;
             }
-            __syncthreads();
         }
-    } else {
-        for (int it = 0; it < iters; ++it) {
-            const int lo = TB - iters + it + 1;
-            const unsigned span = (unsigned)(RY - 1 - 2 * lo);
+        __syncthreads();
 #pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                if (kSkip ? (unsigned)(rr[m] - lo) <= span + 1u : (m < PPT - 1 || threadIdx.x + m * NT < RN)) {
-                    const int l = li[m];
-                    const S dv = (px[m] - s_px[0][l - 1]) + (py[m] - s_py[0][l - LX]);
-                    d[m] = dv;
-                    s_d[l] = dv;
+        for (int m = 0; m < PPT; ++m) {
+            if (kSkip ? (unsigned)(rr[m] - lo) <= span : (m < PPT - 1 || threadIdx.x + m * NT < RN)) {
+                const int l = li[m];
+                // unconditional LDS reads; the boundary masks multiply (a
+                // select around the reads compiles to branches that expose
+                // the LDS latency of every pixel)
+                const S dr = s_d[l + 1];
+                const S dd = s_d[l + LX];
+                S ax, ay;
+                if constexpr (kW) {
+                    ax = (dr - d[m]) * mx[m];
+                    ay = (dd - d[m]) * my[m];
+                } else {
+                    ax = ((dr - d[m]) - gq[m]) * mx[m];
+                    ay = ((dd - d[m]) - gy[m]) * my[m];
                 }
+                chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
+                s_px[l] = px[m];
+                s_py[l] = py[m];
             }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < PPT; ++m) {
-                if (kSkip ? (unsigned)(rr[m] - lo) <= span : (m < PPT - 1 || threadIdx.x + m * NT < RN)) {
-                    const int l = li[m];
-                    // unconditional LDS reads; the boundary masks multiply (a
-                    // select around the reads compiles to branches that expose
-                    // the LDS latency of every pixel)
-                    const S dr = s_d[l + 1];
-                    const S dd = s_d[l + LX];
-                    const S ax = ((dr - d[m]) - gx[m]) * mx[m];
-                    const S ay = ((dd - d[m]) - gy[m]) * my[m];
-                    chambolle_update<S, M>(px[m], py[m], ax, ay, tau);
-                    s_px[0][l] = px[m];
-                    s_py[0][l] = py[m];
-                }
-            }
-            __syncthreads();
         }
+        __syncthreads();
     }
 
 #pragma unroll
@@ -670,7 +652,7 @@ __device__ __forceinline__ double div_p(const S *__restrict__ px, const S *__res
 //   k >= 1: phi_k dt = k (D_{k-1} - D_k)   added to the band holding k
 //           spart  <- block sum of |D_{k-1} - D_k|   (S(t_k) = k/dt * total)
 //   k == K: residual = u_K + K D_K          (u(T) - T u_t(T), forward u_t)
-//   G       = grad(u_{k+1}) / dt           (Chambolle only: data term of the
+//   G       = grad(u_{k+1}) / dt           (F32 Chambolle only: data term of the
 //             next solve; the right and lower neighbours' u_{k+1} are
 //             recomputed here with the same operations their own threads
 //             use, so they match bit for bit)
@@ -723,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void k_flow_step(const SlotDesc *__restri
             resid[q] = uo + (double)K * D;
         uout[q] = un;
         dprev[q] = D;
-        if constexpr (!PD) {
+        if constexpr (!PD && !std::is_same<S, double>::value) {
             if (j < W - 1) {
                 const double unr = uin[q + 1] - dt * div_p(px, py, q + 1, i, j + 1, W);
                 gx[q] = (M)((unr - un) / dt);
@@ -848,11 +830,10 @@ __global__ __launch_bounds__(kThreads) void k_report(const SlotDesc *__restrict_
 // ---------------------------------------------------------------------------
 // launch configuration
 
-// Output tile of the Chambolle kernel, its workgroup size and iteration form.
+// Output tile of the Chambolle kernel and its workgroup size.
 constexpr int kTileX = 32;
 constexpr int kTileY = 32;
 constexpr int kTileThreads = 1024;
-constexpr bool kOneBarrier = false;
 
 int blocks_for(size_t n, int cap)
 {
@@ -889,15 +870,15 @@ template <typename S, typename M> PdhgKernel<S, M> pdhg_kernel(int t, int *tb)
 // Smallest compiled halo width >= t.
 template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
-    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1, kTileThreads, kOneBarrier>; }
-    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2, kTileThreads, kOneBarrier>; }
-    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4, kTileThreads, kOneBarrier>; }
-    if (t <= 5) { *tb = 5; return k_chambolle_tile<S, M, kTileX, kTileY, 5, kTileThreads, kOneBarrier>; }
+    if (t <= 1) { *tb = 1; return k_chambolle_tile<S, M, kTileX, kTileY, 1, kTileThreads>; }
+    if (t <= 2) { *tb = 2; return k_chambolle_tile<S, M, kTileX, kTileY, 2, kTileThreads>; }
+    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kTileY, 4, kTileThreads>; }
+    if (t <= 5) { *tb = 5; return k_chambolle_tile<S, M, kTileX, kTileY, 5, kTileThreads>; }
     if constexpr (max_tb<S>() >= 16) {
-        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16, kTileThreads, kOneBarrier>; }
+        if (t > 8) { *tb = 16; return k_chambolle_tile<S, M, kTileX, kTileY, 16, kTileThreads>; }
     }
     *tb = 8;
-    return k_chambolle_tile<S, M, kTileX, kTileY, 8, kTileThreads, kOneBarrier>;
+    return k_chambolle_tile<S, M, kTileX, kTileY, 8, kTileThreads>;
 }
 
 // Compute units of the current device (cached per device).
@@ -1055,7 +1036,7 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
 } // namespace
 
 size_t state_elem(int precision) { return precision == TVSPEC_PRECISION_F32 ? 4 : 8; }
-size_t g_elem(int precision) { return precision == TVSPEC_PRECISION_F64 ? 8 : 4; }
+size_t g_elem(int precision) { return precision == TVSPEC_PRECISION_F32 ? 4 : 0; }
 
 int plane_blocks(int plane) { return blocks_for((size_t)plane, 1024); }
 
@@ -1064,7 +1045,7 @@ size_t slot_scratch_bytes(int precision, int solver, int H, int W, int C, int K)
     const size_t n = (size_t)C * H * W;
     const size_t nblk = (size_t)plane_blocks(H * W);
     const size_t solver_bytes = solver == kSolverPDHG ? 4 * align256(n * state_elem(precision)) // x[2], xb[2]
-                                                      : 2 * align256(n * g_elem(precision));     // gx, gy
+                                                      : 2 * align256(n * g_elem(precision));     // gx, gy (F32)
     return 4 * align256(n * state_elem(precision))     // px[2], py[2]
            + solver_bytes
            + 3 * align256(n * sizeof(double))           // u[2], dprev
@@ -1092,9 +1073,13 @@ void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W
         d.x[1] = take(n * state_elem(precision));
         d.xb[0] = take(n * state_elem(precision));
         d.xb[1] = take(n * state_elem(precision));
-    } else {
+    } else if (g_elem(precision) > 0) {
         d.gx = take(n * g_elem(precision));
         d.gy = take(n * g_elem(precision));
+        d.x[0] = d.x[1] = d.xb[0] = d.xb[1] = nullptr;
+    } else {
+        // the float64 modes read the data term from u directly
+        d.gx = d.gy = nullptr;
         d.x[0] = d.x[1] = d.xb[0] = d.xb[1] = nullptr;
     }
     d.u[0] = (double *)take(n * sizeof(double));
