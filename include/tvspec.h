@@ -214,7 +214,8 @@ TVSPEC_API int tvspec_decompose_ex(const tvspec_args *args, const tvspec_options
  *                     1..8 for F64 and MIXED; 0 = automatic: 8 for F32, 5 for
  *                     F64, and for MIXED 5 when a launch has at least two
  *                     workgroups per compute unit (several images or
- *                     channels, or planes above ~512x512), else 8).  Results
+ *                     channels, or planes above ~512x512) and planes larger
+ *                     than 64x64, else 8).  Results
  *                     do not depend on it: every variant applies the same
  *                     per-pixel arithmetic in the same order.
  *   stats             TVSPEC_NSTATS doubles (device): [0] max |f - sum of

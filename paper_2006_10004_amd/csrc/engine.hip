@@ -898,20 +898,24 @@ int device_cus()
 }
 
 // Automatic temporal blocking factor.  The 32x32 tile with TB = 8 stages a
-// 48x48 region (2.25 region pixels per output pixel, 70 VGPRs in MIXED): one
-// 1024-thread workgroup per CU.  TB = 5 stages 42x42 (1.72 per output
-// pixel, 52 VGPRs, 46 KB LDS), which lets two workgroups share a CU and hide
-// each other's barriers and loads, at 8/5 the launches.  Measured on MI355X
-// (MIXED): a launch that gives every CU at least two workgroups runs ~30%
-// faster with TB = 5; with one workgroup per CU (a single 512x512 plane)
-// TB = 8 is ~3% faster.  F64 favours TB = 5 in both regimes; F32 keeps
+// 48x48 region (2.25 region pixels per output pixel, 62 VGPRs in MIXED); TB
+// = 5 stages 42x42 (1.72 per output pixel, 48 VGPRs, 46 KB LDS) at 8/5 the
+// launches.  Measured on MI355X (MIXED): with one workgroup per CU (a single
+// 512x512 plane) TB = 8 is 7% faster (16.9 against 18.2 ms for 41 solves);
+// where a launch gives every CU at least two workgroups, TB = 5 is 4-7%
+// faster on planes of 256x256 and up (12 x 3 x 256^2: 36.5 against 38.1 ms;
+// 3 x 1024^2: 41.4 against 44.6 ms), but planes of at most 64x64 (four
+// tiles, half of every region outside the image) keep TB = 8 (256 x 64^2:
+// 48.2 against 51.3 ms).  F64 favours TB = 5 in both regimes; F32 keeps
 // TB = 8.
-int auto_tb(int precision, long long workgroups)
+int auto_tb(int precision, long long workgroups, int H, int W)
 {
     if (precision == TVSPEC_PRECISION_F32)
         return 8;
     if (precision == TVSPEC_PRECISION_F64)
         return 5;
+    if (H <= 64 && W <= 64)
+        return 8;
     return workgroups >= 2LL * device_cus() ? 5 : 8;
 }
 
@@ -983,7 +987,7 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
     const bool pd = cfg.solver == kSolverPDHG;
     int tb = 0;
     const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
-                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C);
+                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C, cfg.H, cfg.W);
     TileKernel<S, M> kt = nullptr;
     PdhgKernel<S, M> kp = nullptr;
     if (pd)
@@ -1103,7 +1107,7 @@ int tile_launches_per_step(const StepConfig &cfg, int nslots)
     const int ntiles = ((cfg.W + kTileX - 1) / kTileX) * ((cfg.H + kTileY - 1) / kTileY);
     int tb = 0;
     const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
-                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C);
+                                              : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C, cfg.H, cfg.W);
     if (cfg.precision == TVSPEC_PRECISION_F32)
         (void)tile_kernel<float, float>(want, &tb);
     else
