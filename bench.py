@@ -59,7 +59,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_chambolle_tile_512x512_mixed_traffic.md")
 PDHG_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_pdhg_tile_512x512_mixed_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "engine.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2006_10004_amd", "csrc", "tile_kernels.h")
 
 
 def measured_traffic(precision, iters_per_launch, record=TRAFFIC_RECORD):
@@ -126,13 +126,30 @@ def percentile(xs, q):
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, vendor, family,
+    model and stepping, and the logical CPUs this process may use (a virtual
+    machine may report only a generic model name, so the numbers are kept
+    beside it)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info.setdefault(k.strip(), v.strip())
     except OSError:
+        return None
+    name = info.get("model name")
+    if not name:
+        return None
+    parts = [name]
+    ids = ["%s %s" % (k, info[k]) for k in ("vendor_id", "cpu family", "model", "stepping") if k in info]
+    if ids:
+        parts.append("(" + ", ".join(ids) + ")")
+    try:
+        parts.append("%d logical CPUs available" % len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
         pass
-    return None
+    return " ".join(parts)
 
 
 def cpu_baseline(f, wl, one_thread_steps=12):

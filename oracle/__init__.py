@@ -49,10 +49,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    sanitized = os.environ.get("TVSPEC_ORACLE_SANITIZE") == "1"
+    path = os.path.join(_HERE, "liboracle_tvspec_san.so") if sanitized else _LIB_PATH
+    if not os.path.exists(path):
         from . import build as _b
-        _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+        _b.build(sanitize=sanitized)
+    lib = ctypes.CDLL(path)
     i, d = ctypes.c_int, ctypes.c_double
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = i

@@ -11,7 +11,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", n) for n in ("engine.hip", "tvspec.hip", "server.hip", "nn.hip")]
+SRCS = [os.path.join(PKG, "csrc", n) for n in ("engine.hip", "tvspec.hip", "server.hip", "nn.hip", "host_logic.cpp")]
 SRC = SRCS[0]
 INC = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtvspec.so")

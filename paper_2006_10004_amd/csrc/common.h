@@ -1,4 +1,5 @@
-// Shared host-side helpers of the tvspec library: error text and HIP checks.
+// Shared host-side helpers of the tvspec library: HIP error checks (the rest
+// of the host logic is in host_logic.h).
 #ifndef TVSPEC_COMMON_H
 #define TVSPEC_COMMON_H
 
@@ -6,26 +7,9 @@
 
 #include <string>
 
+#include "host_logic.h"
 #include "tvspec.h"
 
-namespace tvspec {
-
-// Text of the last error on the calling thread.
-extern thread_local std::string g_last_error;
-
-inline int fail(int code, const std::string &msg)
-{
-    g_last_error = msg;
-    return code;
-}
-
-// Argument validation of the C ABI (host only, before any device work); each
-// returns TVSPEC_OK or TVSPEC_EINVAL with the reason in g_last_error.
-int validate_shape(int B, int H, int W, int C, int iters);
-int validate_image(double dt, int K, const int *edges, int nb);
-int validate_opts(double tau, int warm, int precision, int ipl);
-
-} // namespace tvspec
 
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \

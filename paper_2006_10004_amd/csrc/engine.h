@@ -64,12 +64,6 @@ size_t slot_scratch_bytes(int precision, int solver, int H, int W, int C, int K)
 // dt and nbands are set by the caller.
 void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W, int C, int K);
 
-// Round up to a multiple of 256 bytes.
-inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
-
-// Fill band_rows (host staging for the slot's K + 1 ints) from the edges.
-void band_rows_of(const int *edges, int nbands, int *rows);
-
 struct StepConfig {
     int H, W, C;
     int iters;            // Chambolle iterations per ROF solve

@@ -69,57 +69,6 @@ constexpr int kTuneSteps = 3;     // steps timed per autotuner candidate
 constexpr size_t kChunkMin = 64 << 10;
 constexpr size_t kMinBudget = 1 << 20;
 
-// First-fit allocator of 256-byte-aligned ranges of the pool.
-class RangeAlloc {
-  public:
-    void reset(size_t cap)
-    {
-        free_.clear();
-        free_[0] = cap;
-        used_ = peak_ = 0;
-    }
-    bool alloc(size_t n, size_t *off)
-    {
-        n = align256(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n)
-                continue;
-            const size_t o = it->first, rest = it->second - n;
-            free_.erase(it);
-            if (rest)
-                free_[o + n] = rest;
-            *off = o;
-            used_ += n;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n)
-    {
-        n = align256(n);
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-        used_ -= n;
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-
-  private:
-    std::map<size_t, size_t> free_; // offset -> length
-    size_t used_ = 0, peak_ = 0;
-};
 
 enum class State { Queued, Running, Finishing, Done, Failed };
 

@@ -3,7 +3,8 @@
 Calls only the oracle (and the input generator).  The stored values pin the
 oracle against unintended changes of its arithmetic: the 64x64 shape image
 of seed 0 decomposed with dt = 0.005, K = 60 samples, 200 Chambolle
-iterations per ROF solve, tau = 0.248, warm start, dyadic edges
+iterations per ROF solve, tau = 0.248, cold start (every solve from p = 0,
+the oracle's default), dyadic edges
 {0, 1, 2, 4, 60}.
 """
 import json

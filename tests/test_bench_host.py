@@ -21,7 +21,7 @@ def test_traffic_record_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     rec = json.loads(open(bench.TRAFFIC_RECORD).read().split("```json\n")[1].split("\n```")[0])
     assert rec["traffic_bytes_per_launch"] > 0
     # another source: the record no longer applies, traffic is reported as null
-    other = tmp_path / "engine.hip"
+    other = tmp_path / "tile_kernels.h"
     other.write_text(open(bench.KERNEL_SOURCE).read() + "\n// edited\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
     assert bench.measured_traffic("mixed", 0) is None
