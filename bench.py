@@ -55,6 +55,9 @@ ALU_PEAK_TFLOPS = {"f32": 157.3, "mixed": 78.6, "f64": 78.6}
 # arithmetic type of the path, per precision mode
 DTYPE = {"f32": "f32", "mixed": "f64 (f32-seeded sqrt/rcp)", "f64": "f64"}
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# The band error the surrogate is served at: a size whose rolling judged
+# all-band relative L1 error exceeds it goes to the plain path.
+SURROGATE_MAX_JUDGED_L1 = 0.6
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_chambolle_tile_512x512_mixed_traffic.md")
@@ -316,6 +319,10 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
                     "loss_last25": float(np.mean(losses[-25:])) if losses else None}
     out = torch.cat([net.forward(fte[i:i + batch].contiguous()) for i in range(0, test_images, batch)])
     rec["band_rel_l1"] = S.band_errors(out, bte, rte)
+    pb, pr = S.split_output(out)
+    rec["quality_256"] = Q.band_quality(pb, bte, pr, rte)
+    rec["quality_256"]["definitions"] = ("PSNR with MAX_I = 1, SSIM (11x11 Gaussian window, sigma 1.5), sLMSE "
+                                         "(16x16 patches, stride 8); per band over the held-out images")
     err = nn.tvspec_net_identity_error(fte.contiguous(), out).cpu().numpy()
     rec["identity_error"] = {"mean": float(err.mean()), "max": float(err.max())}
     # inference throughput (batch of 16 at 256^2): HIP events on the stream
@@ -345,13 +352,14 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
                        "flops_per_image": S.conv_flops(256, 256), "traffic": None}
     # serving with fallback on the held-out images
-    svc = S.SurrogateService(net, threshold=1e-2, judge_every=8)
+    svc = S.SurrogateService(net, threshold=1e-2, judge_every=8, max_judged_l1=SURROGATE_MAX_JUDGED_L1)
     _, ts = S.timed(lambda: [svc.decompose(fte[i:i + batch].contiguous()) for i in range(0, test_images, batch)])
     judged = svc.judged
     rec["service_256"] = {"threshold": 1e-2, "requests": test_images, "fallbacks": svc.fallbacks,
                           "judged": len(judged), "s": ts, "MPix_per_s": test_images * 65536 / 1e6 / ts,
                           "judged_all_bands_rel_l1": float(np.mean([j["all_bands"] for j in judged])) if judged
-                          else None}
+                          else None, "max_judged_all_bands_rel_l1": SURROGATE_MAX_JUDGED_L1,
+                          "sizes": svc.size_info()}
     print("bench: surrogate 256x256 evaluation done", file=sys.stderr, flush=True)
     rec["megapixel"] = megapixel_serving(net, mega_sides, mega_requests, seed)
     net.close()
@@ -364,7 +372,7 @@ def surrogate_forward_only(reps, batch=16, side=256, seed=11):
     any weight values): the network's inference throughput and MFMA
     roofline alone, without training; the command to profile its kernels."""
     import torch
-    from paper_2006_10004_amd import nn, surrogate as S
+    from paper_2006_10004_amd import nn, quality as Q, surrogate as S
 
     dev = torch.device("cuda:0")
     net = nn.Net(side, side, batch, seed=seed)
@@ -429,7 +437,7 @@ def megapixel_serving(net, sides, n_req, seed):
     path with the flow the surrogate was trained on, on the same images."""
     import numpy as np
     import torch
-    from paper_2006_10004_amd import nn, surrogate as S, synth
+    from paper_2006_10004_amd import nn, quality as Q, surrogate as S, synth
 
     dev = torch.device("cuda:0")
     p, scale = net.get_params(), net.output_scale
@@ -443,7 +451,7 @@ def megapixel_serving(net, sides, n_req, seed):
     lat_s, lat_p, outs = [], [], []
     num = {k: 0.0 for k in ("band1", "band2", "band3", "band4", "residual", "all_bands")}
     den = dict(num)
-    ident = []
+    ident, quals = [], []
     for side, s in [(sides[0], 1), (sides[-1], 2)]:           # warm both sizes
         fw = S.make_images(1, side, 50000 + s, spec=synth.megapixel_spec(side))
         svc[side].decompose(torch.from_numpy(fw).to(dev))
@@ -461,6 +469,7 @@ def megapixel_serving(net, sides, n_req, seed):
         den["residual"] += float(pr[0].abs().sum())
         num["all_bands"] += float((r["bands"][0].double() - pb[0]).abs().sum())
         den["all_bands"] += float(pb[0].abs().sum())
+        quals.append(Q.band_quality(r["bands"].double(), pb, r["residual"].double(), pr))
         print("bench: megapixel request %dx%d surrogate %.1f ms plain %.1f ms" % (side, side, lat_s[-1], tp * 1e3),
               file=sys.stderr, flush=True)
     mpix = sum(side * side for side, _ in reqs) / 1e6
@@ -473,6 +482,8 @@ def megapixel_serving(net, sides, n_req, seed):
            "plain": {"MPix_per_s": mpix / (sum(lat_p) / 1e3), "p50_ms": percentile(lat_p, 50),
                      "p99_ms": percentile(lat_p, 99), "flow": dict(S.FLOW)},
            "band_rel_l1": {k: num[k] / den[k] for k in num},
+           "quality": {part: {m: float(np.mean([q[part][m] for q in quals])) for m in ("PSNR", "SSIM", "sLMSE")}
+                       for part in quals[0]},
            "identity_error": {"mean": float(np.mean(ident)), "max": float(np.max(ident))}}
     rec["speedup"] = rec["surrogate"]["MPix_per_s"] / rec["plain"]["MPix_per_s"]
     # the plain path with the megapixel workload's own flow (dt 0.002, K 300,

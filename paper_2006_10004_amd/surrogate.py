@@ -149,15 +149,42 @@ def conv_flops(H, W):
 
 class SurrogateService:
     """Decompositions by the network, with the model-driven path as fallback
-    (identity error above `threshold`) and as judge (every `judge_every`-th
-    image, 0 = never)."""
+    and as judge.
 
-    def __init__(self, net: Net, threshold=1e-2, judge_every=16, flow=FLOW, precision="mixed"):
+    - Identity check: an image whose reconstruction-identity error exceeds
+      `threshold` (or is not finite) gets the model-driven decomposition.
+    - Judge: every `judge_every`-th image (0 = never) is also decomposed by
+      the model-driven path and the surrogate's band error measured against
+      it (relative L1 over all bands; the surrogate's result is still the
+      one served, so the judged error is the served error on a sample).
+    - Consequence of the judge: per image size (H, W), the last `window`
+      judged errors are kept; once at least `min_judged` of them average
+      above `max_judged_l1`, that size is demoted and every later image of
+      it is served by the model-driven path (reason "judged").  The identity
+      error alone cannot see bands that are wrong but sum to the right
+      image; the judge can.  `reset()` lifts every demotion (e.g. after the
+      network is retrained)."""
+
+    def __init__(self, net: Net, threshold=1e-2, judge_every=16, flow=FLOW, precision="mixed",
+                 max_judged_l1=0.6, min_judged=4, window=32):
         self.net, self.threshold, self.judge_every = net, threshold, judge_every
         self.flow, self.precision = flow, precision
+        self.max_judged_l1, self.min_judged, self.window = max_judged_l1, min_judged, window
         self.count = 0
-        self.judged = []      # band-error dicts of judged images
-        self.fallbacks = 0
+        self.judged = []      # band-error dicts of judged images (with their size)
+        self.fallbacks = 0    # images served by the model-driven path, any reason
+        self.recent = {}      # (H, W) -> recent judged all-band errors
+        self.demoted = set()  # sizes served by the model-driven path
+
+    def reset(self):
+        self.recent.clear()
+        self.demoted.clear()
+
+    def size_info(self):
+        """Per image size: judged images in the window, their mean all-band
+        error and whether the size is demoted."""
+        return {"%dx%d" % k: {"judged": len(v), "mean_all_bands": float(np.mean(v)) if v else None,
+                              "demoted": k in self.demoted} for k, v in self.recent.items()}
 
     def _plain(self, f):
         n = f.shape[0]
@@ -165,19 +192,38 @@ class SurrogateService:
         return tvspec.tvspec_decompose_batch_dev(f.contiguous(), [fl["dt"]] * n, [fl["K"]] * n, fl["iters"],
                                                  [fl["edges"]] * n, precision=self.precision)
 
+    def _judge(self, size, err):
+        w = self.recent.setdefault(size, [])
+        w.append(err["all_bands"])
+        del w[:-self.window]
+        if len(w) >= self.min_judged and float(np.mean(w)) > self.max_judged_l1:
+            self.demoted.add(size)
+
     def decompose(self, f):
         """f [B, 3, H, W] float32 -> dict(bands [B,4,3,H,W], residual [B,3,H,W]
-        float32, source ['surrogate' | 'plain'] per image, identity_error)."""
+        float32, source ['surrogate' | 'plain'] and reason [None |
+        'identity' | 'judged'] per image, identity_error)."""
+        B, _, H, W = f.shape
+        size = (H, W)
+        if size in self.demoted:
+            plain = self._plain(f)
+            self.count += B
+            self.fallbacks += B
+            bands = torch.stack([o["bands"] for o in plain]).float()
+            res = torch.stack([o["residual"] for o in plain]).float()
+            return {"bands": bands, "residual": res, "source": ["plain"] * B, "reason": ["judged"] * B,
+                    "identity_error": np.full(B, np.nan)}
         out, err = self.net.forward(f, identity=True)
         err = err.cpu().numpy()
         bands, res = split_output(out)
         bands, res = bands.clone(), res.clone()
-        src = ["surrogate"] * f.shape[0]
-        fb = [i for i in range(f.shape[0]) if not (err[i] <= self.threshold)]
+        src = ["surrogate"] * B
+        reason = [None] * B
+        fb = [i for i in range(B) if not (err[i] <= self.threshold)]
         jd = []
         if self.judge_every > 0:
-            jd = [i for i in range(f.shape[0]) if (self.count + i) % self.judge_every == 0 and i not in fb]
-        self.count += f.shape[0]
+            jd = [i for i in range(B) if (self.count + i) % self.judge_every == 0 and i not in fb]
+        self.count += B
         todo = fb + jd
         if todo:
             idx = torch.tensor(todo, device=f.device)
@@ -187,11 +233,15 @@ class SurrogateService:
                     bands[i].copy_(o["bands"])
                     res[i].copy_(o["residual"])
                     src[i] = "plain"
+                    reason[i] = "identity"
                 else:
                     one = out[i:i + 1]
-                    self.judged.append(band_errors(one, o["bands"][None], o["residual"][None]))
+                    e = band_errors(one, o["bands"][None], o["residual"][None])
+                    e["size"] = "%dx%d" % size
+                    self.judged.append(e)
+                    self._judge(size, e)
         self.fallbacks += len(fb)
-        return {"bands": bands, "residual": res, "source": src, "identity_error": err}
+        return {"bands": bands, "residual": res, "source": src, "reason": reason, "identity_error": err}
 
 
 def timed(fn, *a, **k):

@@ -512,6 +512,10 @@ class Server:
                  precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0, use_graphs: bool = True):
         self._h = tvspec_server_create(budget_bytes, tau, warm_start, precision, iters_per_launch, use_graphs)
         self._live = {}
+        # tensors of failed tickets: work enqueued before the failure may
+        # still read or write them until tvspec_server_destroy has
+        # synchronised the server's streams, so they are kept until close()
+        self._graveyard = []
 
     def submit(self, f: torch.Tensor, dt: float, K: int, inner_iters: int, band_edges, sync: bool = True,
                out: dict | None = None):
@@ -542,12 +546,17 @@ class Server:
         self._live[t] = (f, out)
         return t, out
 
+    def _bury(self, ticket):
+        t = self._live.pop(ticket, None)
+        if t is not None:
+            self._graveyard.append(t)
+
     def poll(self, ticket: int):
         """None while pending; {queue_ms, latency_ms} once complete."""
         try:
             r = tvspec_poll(self._h, ticket)
         except TvspecError:
-            self._live.pop(ticket, None)
+            self._bury(ticket)
             raise
         if r is not None:
             self._live.pop(ticket, None)
@@ -556,9 +565,12 @@ class Server:
     def wait(self, ticket: int):
         """Block until the ticket completes; {queue_ms, latency_ms}."""
         try:
-            return tvspec_wait(self._h, ticket)
-        finally:
-            self._live.pop(ticket, None)
+            r = tvspec_wait(self._h, ticket)
+        except TvspecError:
+            self._bury(ticket)
+            raise
+        self._live.pop(ticket, None)
+        return r
 
     def info(self) -> dict:
         return tvspec_server_info(self._h)
@@ -570,6 +582,7 @@ class Server:
                 tvspec_server_destroy(h)
             finally:
                 self._live.clear()
+                self._graveyard.clear()
 
     def __enter__(self):
         return self

@@ -354,3 +354,36 @@ def test_bindings_fail_loudly_without_the_library(tmp_path, module):
                        env=dict(os.environ, PYTHONPATH=str(tmp_path)), capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "is not built" in r.stderr
+
+
+def test_server_keeps_tensors_of_failed_tickets_until_close(tv, monkeypatch):
+    """A ticket that fails (the server failed, e.g. an allocation error) keeps
+    its tensors alive until close() has destroyed the server, because work
+    enqueued before the failure may still use them; completed tickets drop
+    theirs at once.  Bookkeeping only: the C calls are stubbed, no device."""
+    srv = object.__new__(tv.Server)
+    srv._h, srv._live, srv._graveyard = "handle", {}, []
+    calls = []
+
+    def poll(h, t):
+        if t == 2:
+            raise tv.TvspecError(tv.TVSPEC_EDEVICE, "server failed")
+        return {"queue_ms": 0.0, "latency_ms": 1.0}
+
+    def wait(h, t):
+        raise tv.TvspecError(tv.TVSPEC_ENOMEM, "server failed")
+
+    monkeypatch.setattr(tv, "tvspec_poll", poll)
+    monkeypatch.setattr(tv, "tvspec_wait", wait)
+    monkeypatch.setattr(tv, "tvspec_server_destroy", lambda h: calls.append(h))
+    for t in (1, 2, 3):
+        srv._live[t] = ("f%d" % t, {"out": t})
+    assert srv.poll(1) == {"queue_ms": 0.0, "latency_ms": 1.0}
+    assert 1 not in srv._live and srv._graveyard == []
+    with pytest.raises(tv.TvspecError):
+        srv.poll(2)
+    with pytest.raises(tv.TvspecError):
+        srv.wait(3)
+    assert srv._live == {} and srv._graveyard == [("f2", {"out": 2}), ("f3", {"out": 3})]
+    srv.close()
+    assert calls == ["handle"] and srv._graveyard == [] and srv._h is None

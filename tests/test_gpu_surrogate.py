@@ -146,3 +146,41 @@ def test_non_finite_output_falls_back(mods):
     for i in range(2):
         assert torch.equal(r["bands"][i], alone[i][0].float())
     net.close()
+
+
+def test_judged_error_demotes_the_size(mods):
+    """The judged band error has a consequence: once the rolling mean of
+    the judged errors of an image size exceeds the stated bound, later
+    images of that size are served by the model-driven path (the same as
+    computed alone), and reset() lifts it.  A fresh network (bands 0) is
+    judged at error exactly 1."""
+    nn, S, tv = mods
+    net = nn.Net(64, 64, 4, seed=1)
+    svc = S.SurrogateService(net, threshold=1e-2, judge_every=1, flow=FLOW, max_judged_l1=0.5, min_judged=2)
+    r = svc.decompose(images(S, 2, 64, 600))
+    assert r["source"] == ["surrogate"] * 2 and r["reason"] == [None, None]
+    assert [e["all_bands"] for e in svc.judged] == [1.0, 1.0]
+    assert svc.size_info()["64x64"] == {"judged": 2, "mean_all_bands": 1.0, "demoted": True}
+    f = images(S, 3, 64, 700)
+    r = svc.decompose(f)
+    assert r["source"] == ["plain"] * 3 and r["reason"] == ["judged"] * 3
+    alone = plain_alone(tv, f)
+    for i in range(3):
+        assert torch.equal(r["bands"][i], alone[i][0].float())
+        assert torch.equal(r["residual"][i], alone[i][1].float())
+    assert svc.fallbacks == 3
+    svc.reset()
+    r = svc.decompose(images(S, 1, 64, 800))
+    assert r["source"] == ["surrogate"]
+    net.close()
+
+
+def test_judged_error_within_bound_keeps_the_network(mods):
+    nn, S, tv = mods
+    net = nn.Net(64, 64, 4, seed=1)
+    svc = S.SurrogateService(net, threshold=1e-2, judge_every=1, flow=FLOW, max_judged_l1=1.5, min_judged=2)
+    for seed in (900, 910, 920):
+        r = svc.decompose(images(S, 2, 64, seed))
+        assert r["source"] == ["surrogate"] * 2
+    assert svc.size_info()["64x64"]["demoted"] is False and svc.fallbacks == 0
+    net.close()
