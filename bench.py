@@ -285,7 +285,7 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     latency and the surrogate's band error against the plain path."""
     import numpy as np
     import torch
-    from paper_2006_10004_amd import nn, surrogate as S, synth
+    from paper_2006_10004_amd import nn, quality as Q, surrogate as S, synth
 
     dev = torch.device("cuda:0")
     rec = {"workload": "3x256x256 synthetic shape images (half 40-shape images, half crops of 1024x1024 "
@@ -372,7 +372,7 @@ def surrogate_forward_only(reps, batch=16, side=256, seed=11):
     any weight values): the network's inference throughput and MFMA
     roofline alone, without training; the command to profile its kernels."""
     import torch
-    from paper_2006_10004_amd import nn, quality as Q, surrogate as S
+    from paper_2006_10004_amd import nn, surrogate as S
 
     dev = torch.device("cuda:0")
     net = nn.Net(side, side, batch, seed=seed)
