@@ -21,11 +21,13 @@
 //                  fused in the epilogue, which leaves through an LDS tile in
 //                  16-byte pieces.
 //   k_wgrad        weight gradient, reduction over pixels: a workgroup takes
-//                  64 output channels x 128 values of k over a range of
-//                  pixels, stages 64-pixel chunks of dY and of the shifted X
-//                  in LDS transposed (k-major), so MFMA operands are 16-byte
-//                  LDS reads; per-range partial sums are added in a fixed
-//                  order by k_reduce_rows (deterministic).
+//                  16 OW output x 16 WC input channels x all 9 taps over a
+//                  range of 4 x 32 pixel tiles; each tile's dY and X (with
+//                  its halo) are staged in LDS once, channels-last, and every
+//                  tap's operand is the X tile read at a shift through the
+//                  transposing LDS read (ds_read_b64_tr_b16); per-range
+//                  partial sums are added in a fixed order by k_reduce_rows
+//                  (deterministic).
 //   the rest       packing, 2x2 max-pooling, nearest upsampling with skip
 //                  concatenation, their gradients (ReLU masks fused), the
 //                  normalised MSE loss and its gradient, Adam.
@@ -528,163 +530,228 @@ __global__ __launch_bounds__(kT) void k_flip_transpose(const __bf16 *__restrict_
 
 // ---------------------------------------------------------------------------
 // weight gradient
+//
+// dW[o][tap][c] = sum over pixels p of dY[p][o] X[p + offset(tap)][c]: a
+// GEMM whose reduction index is the pixel.  A workgroup of WC waves owns
+// 16 OW output channels x 16 WC input channels x all 9 taps and walks a
+// range of pixel tiles (kGR rows x kGC columns of one image).  Per tile,
+// the dY tile and the X tile with its one-pixel halo are staged in LDS once,
+// channels-last as they are stored (16-byte pieces, from registers loaded
+// one tile ahead), and every tap's operand is the X tile read at that tap's
+// shift: each X value leaves L2 about 1.6 times per tile instead of 9.
+//
+// The MFMA operands need 8 consecutive pixels of one channel per lane, the
+// transpose of that layout; ds_read_b64_tr_b16 (gfx950) delivers it.  In
+// each group of 16 lanes it gives lane 4a + e, in slot j, element e of the 8
+// bytes addressed by lane a + 4j.  So lane s of group g addresses pixel
+// 8g + (s >> 2) (+ 4 for the operand's upper half) at the 4-channel piece
+// s & 3 of a 16-channel fragment, and receives fragment row s at pixels
+// 8g .. 8g + 3 (+ 4): exactly the operand layout of
+// v_mfma_f32_16x16x32_bf16.  The 4 pixels of one group sit at a pitch that
+// is an odd multiple of 32 bytes, so their 32-byte pieces fall in distinct
+// banks.
+//
+// Wave w owns input channels 16 w .. 16 w + 15 of the tile: per pixel row
+// it reads OW dY fragments and 9 shifted X fragments for 9 OW MFMAs.  The
+// workgroups of the first channel tile also form the bias gradient (the sum
+// of dY over the pixels) on wave 0, as products with a fragment of ones.
+// Per-range partial sums are added in a fixed order by k_reduce_rows
+// (deterministic).
+constexpr int kGR = 4;          // pixel rows per tile
+constexpr int kGC = 32;         // pixel columns per tile: one 32-wide MFMA k step per row
+constexpr int kGHX = kGC + 2;   // X tile columns with the halo
 
-constexpr int kWChunk = 64;             // pixels per LDS stage
-constexpr int kWPitch = kWChunk + 8;    // LDS row pitch (elements), 16-byte aligned rows
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef short short8v __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+typedef __attribute__((address_space(3))) short4v lds_short4;
 
-constexpr int kWK = 128;  // values of k per workgroup tile
-
-// Column of pixel `col` (0..63) in LDS row `row` of a transposed staging
-// tile: each group of 8 rows is rotated by 8 (row / 8 mod 8) columns, so the
-// 8 two-byte stores of one instruction (rows 8 apart, same column) fall in
-// different banks; 8 consecutive pixels stay consecutive and 16-byte
-// aligned for the MFMA operand reads.
-__device__ __forceinline__ int swz(int row, int col) { return (col + (((row >> 3) & 7) << 3)) & (kWChunk - 1); }
-
-// part[s][o][k] = sum over pixels of range s of dY[p][o] * A[p][k], for the
-// 64 x kWK tile (o0, k0) of (Cout, 9 Cin); with bpart != nullptr the
-// workgroups of the first k tile also write bpart[s][o] = sum of dY[p][o]
-// over the range (the bias gradient's partial sums).  Range s covers chunks
-// [s * cps, (s + 1) * cps) of kWChunk pixels.
-__global__ __launch_bounds__(kT) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
-                                              float *__restrict__ part, float *__restrict__ bpart, int B, int H,
-                                              int W, int Cin, int Cout, int cps)
+// One MFMA operand from two transposed reads, 4 pixel rows apart.
+__device__ __forceinline__ bf16x8 tr_operand(const lds_u8 *p, int half)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sA[64 * kWPitch];  // [o][pixel]
-    __shared__ __attribute__((aligned(16))) __bf16 sB[kWK * kWPitch]; // [k][pixel]
+    const short4v lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_short4 *)p);
+    const short4v hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_short4 *)(p + half));
+    const short8v v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+template <int OW, int WC>
+__global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
+                                                   float *__restrict__ part, float *__restrict__ bpart, int H, int W,
+                                                   int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles,
+                                                   int tpr)
+{
+    constexpr int kNT = 64 * WC;
+    constexpr int kOT = 16 * OW;               // output channels of the workgroup
+    constexpr int kCT = 16 * WC;               // input channels of the workgroup
+    constexpr int kYP = 32 * (OW | 1);         // LDS bytes per pixel, dY tile
+    constexpr int kXP = 32 * (WC | 1);         // LDS bytes per pixel, X tile
+    constexpr int kYG = kOT / 8;               // 16-byte pieces per pixel
+    constexpr int kXG = kCT / 8;
+    constexpr int kYPix = kGR * kGC;
+    constexpr int kXPix = (kGR + 2) * kGHX;
+    constexpr int kYItems = kYPix * kYG;
+    constexpr int kXItems = kXPix * kXG;
+    constexpr int kYPer = (kYItems + kNT - 1) / kNT;
+    constexpr int kXPer = (kXItems + kNT - 1) / kNT;
+    constexpr int kYBytes = kYPix * kYP;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kYBytes + kXPix * kXP];
+    const lds_u8 *const sY = (const lds_u8 *)smem;
+    const lds_u8 *const sX = sY + kYBytes;
+
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
+    const int ct = blockIdx.x % n_ct;
+    const int c0 = ct * kCT;
+    const int o0 = (blockIdx.x / n_ct) * kOT;
+    const int s = blockIdx.y;
+    const int t0 = s * tpr;
+    const int t1 = min(tiles, t0 + tpr);
     const int K = 9 * Cin;
-    const int k0 = blockIdx.x * kWK;
-    const int o0 = blockIdx.y * 64;
-    const int s = blockIdx.z;
-    const long long P = (long long)B * H * W;
-    const long long HW = (long long)H * W;
-    const bool do_bias = bpart != nullptr && blockIdx.x == 0;
+    const bool do_bias = bpart != nullptr && ct == 0 && wave == 0;
 
-    // wave (wo, wk) = (wave / 2, wave % 2) computes output channels
-    // o0 + 32 wo .. +31 x k values k0 + 64 wk .. +63: 2 x 4 fragments, six
-    // operand reads per eight MFMAs (a 16 x 128 strip per wave needs nine)
-    const int wo = wave >> 1;
-    const int wk = wave & 1;
-    floatx4 acc[2][4];
+    floatx4 acc[OW][9];
+    floatx4 bacc[OW];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int f = 0; f < OW; ++f) {
+        bacc[f] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            acc[a][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;
+        for (int tap = 0; tap < 9; ++tap)
+            acc[f][tap] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    bf16x8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        ones[j] = (__bf16)1.0f;
 
-    // staging roles: dY, thread t: pixel t / 8 (+32), channels (t % 8) * 8;
-    // X, thread t: pixel t / 16 (+16, +32, +48), k values (t % 16) * 8
-    const int spa = threadIdx.x >> 3;
-    const int sga = threadIdx.x & 7;
-    const int oo = o0 + sga * 8;
-    const bool oval = oo < Cout;
-    const int spb = threadIdx.x >> 4;
-    const int sgb = threadIdx.x & 15;
-    const int ko = k0 + sgb * 8;
-    const bool kval = ko < K;
-    const int tap = kval ? ko / Cin : 0;
-    const int ch = kval ? ko - tap * Cin : 0;
-    const int dy = tap / 3 - 1;
-    const int dx = tap - (tap / 3) * 3 - 1;
-
-    // the chunk's global loads go to registers one chunk ahead
-    bf16x8 va[2], vb[4];
-    auto load_chunk = [&](long long pbase) {
+    // tile t: image t / (tiles_y tiles_x), rows kGR ty .., columns kGC tx ..;
+    // pieces outside the image or past the channel counts are zero
+    bf16x8 vy[kYPer], vx[kXPer];
+    auto load = [&](int t) {
+        const int tx = t % tiles_x;
+        const int ty = (t / tiles_x) % tiles_y;
+        const int b = t / (tiles_x * tiles_y);
+        const int y0 = ty * kGR;
+        const int x0 = tx * kGC;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const long long p = pbase + spa + 32 * h;
-            va[h] = zero8();
-            if (p < P && oval)
-                va[h] = *(const bf16x8 *)(dY + (size_t)p * Cout + oo);
+        for (int j = 0; j < kYPer; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            const __bf16 *src = (const __bf16 *)kZero16;
+            if (i < kYItems) {
+                const int pix = i / kYG;
+                const int grp = i - pix * kYG;
+                const int r = pix / kGC;
+                const int yy = y0 + r;
+                const int xx = x0 + pix - r * kGC;
+                const int o = o0 + 8 * grp;
+                if (yy < H && xx < W && o < Cout)
+                    src = dY + ((size_t)((size_t)b * H + yy) * W + xx) * Cout + o;
+            }
+            vy[j] = *(const global_bf16x8 *)src;
         }
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const long long p = pbase + spb + 16 * h;
-            vb[h] = zero8();
-            if (p < P && kval) {
-                const int b = (int)(p / HW);
-                const int rem = (int)(p - (long long)b * HW);
-                const int yy = rem / W + dy;
-                const int xx = rem - (rem / W) * W + dx;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    vb[h] = *(const bf16x8 *)(X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + ch);
+        for (int j = 0; j < kXPer; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            const __bf16 *src = (const __bf16 *)kZero16;
+            if (i < kXItems) {
+                const int pix = i / kXG;
+                const int grp = i - pix * kXG;
+                const int hr = pix / kGHX;
+                const int yy = y0 + hr - 1;
+                const int xx = x0 + pix - hr * kGHX - 1;
+                const int c = c0 + 8 * grp;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W && c < Cin)
+                    src = X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + c;
+            }
+            vx[j] = *(const global_bf16x8 *)src;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < kYPer; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            if (i < kYItems) {
+                const int pix = i / kYG;
+                *(bf16x8 *)(smem + pix * kYP + 16 * (i - pix * kYG)) = vy[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kXPer; ++j) {
+            const int i = threadIdx.x + j * kNT;
+            if (i < kXItems) {
+                const int pix = i / kXG;
+                *(bf16x8 *)(smem + kYBytes + pix * kXP + 16 * (i - pix * kXG)) = vx[j];
             }
         }
     };
-    const long long pfirst = (long long)s * cps * kWChunk;
-    const int nchunk = (int)min((long long)cps, (P - pfirst + kWChunk - 1) / kWChunk);
-    if (nchunk > 0)
-        load_chunk(pfirst);
-    for (int chunk = 0; chunk < nchunk; ++chunk) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int pl = spa + 32 * h;
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                sA[(sga * 8 + j) * kWPitch + swz(sga * 8 + j, pl)] = va[h][j];
-        }
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int pl = spb + 16 * h;
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                sB[(sgb * 8 + j) * kWPitch + swz(sgb * 8 + j, pl)] = vb[h][j];
-        }
+
+    // this lane's transposed-read addresses: pixel 8 g + (r16 >> 2) of a row
+    // step, 4-channel piece r16 & 3 of a fragment
+    const int kp = 8 * g + (r16 >> 2);
+    const int cq = 8 * (r16 & 3);
+    const lds_u8 *const pY = sY + kp * kYP + cq;
+    const lds_u8 *const pX = sX + kp * kXP + 32 * wave + cq;
+
+    if (t0 < t1)
+        load(t0);
+    for (int t = t0; t < t1; ++t) {
+        store();
         __syncthreads();
-        if (chunk + 1 < nchunk)
-            load_chunk(pfirst + (long long)(chunk + 1) * kWChunk);
-        if (do_bias && threadIdx.x < 64) {
+        if (t + 1 < t1)
+            load(t + 1);
+#pragma unroll 1
+        for (int r = 0; r < kGR; ++r) {
+            bf16x8 a[OW];
 #pragma unroll
-            for (int q = 0; q < kWChunk; q += 8) {
-                const bf16x8 v = *(const bf16x8 *)(sA + threadIdx.x * kWPitch + q);
+            for (int f = 0; f < OW; ++f)
+                a[f] = tr_operand(pY + r * kGC * kYP + 32 * f, 4 * kYP);
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    bacc += (float)v[j];
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3;
+                const int dx = tap - 3 * dy;
+                const bf16x8 bx = tr_operand(pX + ((r + dy) * kGHX + dx) * kXP, 4 * kXP);
+#pragma unroll
+                for (int f = 0; f < OW; ++f)
+                    acc[f][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], bx, acc[f][tap], 0, 0, 0);
             }
-        }
+            if (do_bias) {
 #pragma unroll
-        for (int kk = 0; kk < kWChunk; kk += 32) {
-            bf16x8 av[2], bv[4];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const int ra = wo * 32 + a * 16 + r16;
-                av[a] = *(const bf16x8 *)(sA + ra * kWPitch + swz(ra, kk + 8 * g));
+                for (int f = 0; f < OW; ++f)
+                    bacc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], ones, bacc[f], 0, 0, 0);
             }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int rb = wk * 64 + j * 16 + r16;
-                bv[j] = *(const bf16x8 *)(sB + rb * kWPitch + swz(rb, kk + 8 * g));
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[a][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[j], acc[a][j], 0, 0, 0);
         }
         __syncthreads();
     }
-    float *out = part + (size_t)s * Cout * K;
+
+    // result lane layout: column r16 (input channel), rows 4 g .. 4 g + 3
+    // (output channels) of each fragment
+    float *const out = part + (size_t)s * Cout * K;
+    const int c = c0 + 16 * wave + r16;
+    if (c < Cin) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = k0 + wk * 64 + j * 16 + r16;
-        if (k >= K)
-            continue;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int f = 0; f < OW; ++f)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int o = o0 + wo * 32 + a * 16 + 4 * g + i;
-                if (o < Cout)
-                    out[(size_t)o * K + k] = acc[a][j][i];
+                const int o = o0 + 16 * f + 4 * g + i;
+                if (o < Cout) {
+#pragma unroll
+                    for (int tap = 0; tap < 9; ++tap)
+                        out[(size_t)o * K + tap * Cin + c] = acc[f][tap][i];
+                }
             }
     }
-    if (do_bias && threadIdx.x < 64 && o0 + (int)threadIdx.x < Cout)
-        bpart[(size_t)s * Cout + o0 + threadIdx.x] = bacc;
+    if (do_bias && r16 == 0) {
+#pragma unroll
+        for (int f = 0; f < OW; ++f)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = o0 + 16 * f + 4 * g + i;
+                if (o < Cout)
+                    bpart[(size_t)s * Cout + o] = bacc[f][i];
+            }
+    }
 }
 
 // Fixed-order sum of the rows of part [ns][n] (n a multiple of 4, part
@@ -1371,25 +1438,65 @@ void reduce_rows(float *part, int ns, size_t n, float *out, hipStream_t st)
     hipLaunchKernelGGL(k_reduce_rows, dim3(grid_for(n4)), dim3(kT), 0, st, part, ns, stride, n, out);
 }
 
+// Output and input channels per workgroup of the weight gradient: 16 OW and
+// 16 WC with OW, WC in {1, 3, 4}, each the one that pads the channel count
+// least (the larger on a tie); OW is then capped at WC, since the wider
+// output tiles need the registers that fewer threads per workgroup spend on
+// the next tile's loads.
+int wgrad_width(int C)
+{
+    int best = 4, best_pad = 1 << 30;
+    for (int m : {4, 3, 1}) {
+        const int pad = (C + 16 * m - 1) / (16 * m) * 16 * m;
+        if (pad < best_pad) {
+            best = m;
+            best_pad = pad;
+        }
+    }
+    return best;
+}
+
+template <int OW, int WC>
+void wgrad_launch(dim3 grid, const __bf16 *x, const __bf16 *dy, float *part, float *bp, int H, int W, int Cin,
+                  int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_wgrad<OW, WC>), grid, dim3(64 * WC), 0, st, x, dy, part, bp, H, W, Cin, Cout, n_ct,
+                       tiles_x, tiles_y, tiles, tpr);
+}
+
 int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, float *dw,
                float *db, hipStream_t st)
 {
-    const long long P = (long long)B * H * W;
+    const int WC = wgrad_width(Cin);
+    const int OW = wgrad_width(Cout) > WC ? (WC == 1 ? 1 : 3) : wgrad_width(Cout);
+    const int n_ot = (Cout + 16 * OW - 1) / (16 * OW);
+    const int n_ct = (Cin + 16 * WC - 1) / (16 * WC);
+    const int tiles_x = (W + kGC - 1) / kGC, tiles_y = (H + kGR - 1) / kGR;
+    const long long tiles = (long long)B * tiles_x * tiles_y;
     const int K = 9 * Cin;
-    const int tk = (K + kWK - 1) / kWK, to = (Cout + 63) / 64;
-    const long long chunks = (P + kWChunk - 1) / kWChunk;
-    // enough ranges to give the device ~2048 workgroups
-    long long ns = 2048 / ((long long)tk * to);
-    ns = ns < 1 ? 1 : ns;
-    ns = ns > chunks ? chunks : ns;
-    const int cps = (int)((chunks + ns - 1) / ns);
-    ns = (chunks + cps - 1) / cps;
     const size_t n = (size_t)Cout * K;
+    const long long per_range = (long long)n_ot * n_ct;
+    // pixel ranges: ~1024 workgroups in all, as long as the partial sums stay
+    // within 64 MB, but at least enough to give every CU one workgroup
+    long long ns = 1024 / per_range;
+    const long long cap = (64LL << 20) / (long long)((n + Cout) * sizeof(float));
+    ns = ns > cap ? cap : ns;
+    const long long floor_ns = (256 + per_range - 1) / per_range;
+    ns = ns < floor_ns ? floor_ns : ns;
+    ns = ns > tiles ? tiles : ns;
+    ns = ns < 1 ? 1 : ns;
+    const long long tpr = (tiles + ns - 1) / ns;
+    ns = (tiles + tpr - 1) / tpr;
     const size_t need = ((size_t)ns * n + (size_t)ns * Cout) * sizeof(float);
     TVSPEC_TRY(ensure((void **)&wk.part, &wk.part_bytes, need));
     float *bp = db ? wk.part + (size_t)ns * n : nullptr;
-    hipLaunchKernelGGL(k_wgrad, dim3(tk, to, (unsigned)ns), dim3(kT), 0, st, x, dy, wk.part, bp, B, H, W, Cin, Cout,
-                       cps);
+    const dim3 grid((unsigned)per_range, (unsigned)ns);
+    const int ti = (int)tiles, tp = (int)tpr;
+#define TVSPEC_WG(ow, wc)                                                                                       \
+    if (OW == ow && WC == wc)                                                                                   \
+        wgrad_launch<ow, wc>(grid, x, dy, wk.part, bp, H, W, Cin, Cout, n_ct, tiles_x, tiles_y, ti, tp, st);
+    TVSPEC_WG(1, 1) TVSPEC_WG(1, 3) TVSPEC_WG(1, 4) TVSPEC_WG(3, 3) TVSPEC_WG(3, 4) TVSPEC_WG(4, 4)
+#undef TVSPEC_WG
     reduce_rows(wk.part, (int)ns, n, dw, st);
     if (db)
         reduce_rows(bp, (int)ns, (size_t)Cout, db, st);
