@@ -259,6 +259,11 @@ SERVING = {
                 "with the side), side uniform in {128, 256, 512, 1024}, Poisson arrivals",
     "C": 3, "sides": [128, 256, 512, 1024], "dt": 0.005, "K": 100, "inner_iters": 150, "n_bands": 4,
 }
+# A second Poisson run at a fixed arrival rate, so that latency percentiles
+# compare across builds at one offered load (the other run's rate follows
+# the measured burst throughput).
+SERVING_FIXED_RATE = 12.0
+SERVING_FIXED_REQUESTS = 384
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
@@ -595,10 +600,11 @@ def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
     rec = {"workload": sv["workload"], "config": {k: v for k, v in sv.items() if k != "workload"},
            "precision": precision, "budget_GiB": budget_gb}
     with tvspec.Server(budget, precision=precision) as srv:
-        # warm the buckets (graphs, autotuner) on a few requests of every side
+        # warm the buckets (graphs, and the autotuner's timed steps: 6
+        # candidates x 3 steps) on one request of every side
         warm = [(s, imgs[s][0], None) for s in sv["sides"]]
         for s, f, _ in warm:
-            srv.submit(f, sv["dt"], 2, sv["inner_iters"], [0, 2])
+            srv.submit(f, sv["dt"], 20, sv["inner_iters"], [0, 20])
         while srv.info()["completed"] < len(warm):
             time.sleep(0.001)
         jobs = make_jobs(burst)
@@ -613,8 +619,16 @@ def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
         rec["poisson"] = run(srv, jobs, list(arrivals))
         rec["poisson"]["rate_req_per_s"] = r
         del jobs
+        print("bench: serving Poisson run done (p99 %.0f ms)" % rec["poisson"]["p99_ms"], file=sys.stderr,
+              flush=True)
+        jobs = make_jobs(SERVING_FIXED_REQUESTS)
+        arrivals = np.cumsum(rng.exponential(1.0 / SERVING_FIXED_RATE, size=SERVING_FIXED_REQUESTS))
+        arrivals -= arrivals[0]
+        rec["poisson_fixed_rate"] = run(srv, jobs, list(arrivals))
+        rec["poisson_fixed_rate"]["rate_req_per_s"] = SERVING_FIXED_RATE
+        del jobs
         info = srv.info()
-    rec["server"] = {k: info[k] for k in ("max_in_flight", "graph_builds", "buckets", "steps", "peak_bytes")}
+    rec["server"] = {k: info[k] for k in ("max_in_flight", "graph_builds", "buckets", "steps", "replays", "peak_bytes")}
     return rec
 
 

@@ -135,6 +135,13 @@ TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
  *          device_ptrs       0: host buffers, the call is synchronous;
  *                            1: device buffers, work enqueued on `stream`
  *          stream            hipStream_t for device_ptrs = 1 (NULL = null stream)
+ *          tile_shape        output pixels per workgroup of the Chambolle
+ *                            tile kernel: TVSPEC_TILE_SQUARE (32 x 32 on
+ *                            1024 threads, the default) or TVSPEC_TILE_NARROW
+ *                            (32 x 16 on 512 threads: twice the workgroups
+ *                            for images too small to fill the device;
+ *                            iters_per_launch <= 8, Chambolle only).  Results
+ *                            do not depend on the shape.
  * rep:   NULL = no report.  Otherwise the call waits until its work is
  *        complete (also with device_ptrs = 1) and fills
  *          recon_err   max |f - sum of bands - residual|
@@ -146,13 +153,15 @@ TVSPEC_API int tvspec_decompose(const float *f, int H, int W, int C, double dt, 
  *          total_ms    host wall time of the whole call
  *
  * Errors: as tvspec_decompose_dev, TVSPEC_EINVAL for a bad solver,
- * device_ptrs or step, and TVSPEC_ENUMERIC for non-finite input: with host
+ * device_ptrs, tile_shape or step, and TVSPEC_ENUMERIC for non-finite input: with host
  * buffers before any device work; with device buffers when a report is
  * requested (after the work: the outputs are then meaningless; without a
  * report the count is only in stats[2]).
  */
 #define TVSPEC_SOLVER_CHAMBOLLE 0
 #define TVSPEC_SOLVER_PDHG 1
+#define TVSPEC_TILE_SQUARE 0
+#define TVSPEC_TILE_NARROW 1
 
 typedef struct tvspec_args {
     const float *f;
@@ -177,6 +186,7 @@ typedef struct tvspec_options {
     int iters_per_launch;
     int device_ptrs;
     void *stream;
+    int tile_shape;
 } tvspec_options;
 
 typedef struct tvspec_report {
@@ -386,6 +396,7 @@ typedef struct tvspec_result {
 typedef struct tvspec_server_stats {
     unsigned long long submitted, admitted, completed;
     unsigned long long steps;        /* bucket steps enqueued */
+    unsigned long long replays;      /* step runs enqueued (one graph replay each; up to 4 steps) */
     unsigned long long graph_builds; /* step graphs captured */
     int buckets;
     int max_in_flight;               /* most requests admitted at once */

@@ -64,6 +64,12 @@ size_t slot_scratch_bytes(int precision, int solver, int H, int W, int C, int K)
 // dt and nbands are set by the caller.
 void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W, int C, int K);
 
+// Tile shapes of the Chambolle tile kernel (results do not depend on the
+// shape): 32 x 32 output pixels on 1024 threads, or 32 x 16 on 512 threads
+// (twice the workgroups for small launches; TB 4, 5 or 8).
+constexpr int kTileShapeSquare = 0;
+constexpr int kTileShapeNarrow = 1;
+
 struct StepConfig {
     int H, W, C;
     int iters;            // Chambolle iterations per ROF solve
@@ -74,6 +80,7 @@ struct StepConfig {
     int timed = 1;        // 0: never record benchmark timing (graph capture)
     int solver = kSolverChambolle;
     double sigma = 0.0;   // PDHG dual step (tau is its primal step)
+    int tile = kTileShapeSquare; // Chambolle tile shape (the primal-dual solver uses the square one)
 };
 
 // Tile-kernel launches per engine_step over a table of nslots slots (the

@@ -402,6 +402,20 @@ template <typename S, typename M> PdhgKernel<S, M> pdhg_kernel(int t, int *tb)
     return k_pdhg_tile<S, M, kTileX, kTileY, 8, kTileThreads>;
 }
 
+// The narrow tile shape (kTileShapeNarrow): 32 x 16 output pixels on 512
+// threads, for launches that give the device too few 32 x 32 workgroups;
+// compiled for TB = 4, 5 and 8.
+constexpr int kNarrowY = 16;
+constexpr int kNarrowThreads = 512;
+
+template <typename S, typename M> TileKernel<S, M> narrow_tile_kernel(int t, int *tb)
+{
+    if (t <= 4) { *tb = 4; return k_chambolle_tile<S, M, kTileX, kNarrowY, 4, kNarrowThreads>; }
+    if (t <= 5) { *tb = 5; return k_chambolle_tile<S, M, kTileX, kNarrowY, 5, kNarrowThreads>; }
+    *tb = 8;
+    return k_chambolle_tile<S, M, kTileX, kNarrowY, 8, kNarrowThreads>;
+}
+
 // Smallest compiled halo width >= t.
 template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
@@ -516,10 +530,13 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
                                                 hipStream_t st, long long live_planes)
 {
     const int plane = cfg.H * cfg.W;
-    const int ntx = (cfg.W + kTileX - 1) / kTileX;
-    const int nty = (cfg.H + kTileY - 1) / kTileY;
-    const int ntiles = ntx * nty;
     const bool pd = cfg.solver == kSolverPDHG;
+    const bool narrow = !pd && cfg.tile == kTileShapeNarrow;
+    const int tile_y = narrow ? kNarrowY : kTileY;
+    const int threads = narrow ? kNarrowThreads : kTileThreads;
+    const int ntx = (cfg.W + kTileX - 1) / kTileX;
+    const int nty = (cfg.H + tile_y - 1) / tile_y;
+    const int ntiles = ntx * nty;
     int tb = 0;
     const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
                                               : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C, cfg.H, cfg.W);
@@ -527,6 +544,8 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
     PdhgKernel<S, M> kp = nullptr;
     if (pd)
         kp = pdhg_kernel<S, M>(want, &tb);
+    else if (narrow)
+        kt = narrow_tile_kernel<S, M>(want, &tb);
     else
         kt = tile_kernel<S, M>(want, &tb);
     const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
@@ -549,7 +568,7 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
                                cfg.W, cfg.C, ntx, ntiles, (S)cfg.tau, (S)cfg.sigma, (S)(1.0 / (1.0 + cfg.tau)), it,
                                done == 0 ? 1 : 0, zero_in);
         else
-            hipLaunchKernelGGL(kt, dim3(ntiles, nslots * cfg.C), dim3(kTileThreads), 0, st, d_slots, cur, cfg.H,
+            hipLaunchKernelGGL(kt, dim3(ntiles, nslots * cfg.C), dim3(threads), 0, st, d_slots, cur, cfg.H,
                                cfg.W, cfg.C, ntx, ntiles, (S)cfg.tau, it, zero_in);
         if (timed) {
             ++g_timing.launches;
@@ -632,11 +651,17 @@ void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W
 
 int tile_launches_per_step(const StepConfig &cfg, int nslots)
 {
-    const int ntiles = ((cfg.W + kTileX - 1) / kTileX) * ((cfg.H + kTileY - 1) / kTileY);
+    const bool narrow = cfg.solver != kSolverPDHG && cfg.tile == kTileShapeNarrow;
+    const int tile_y = narrow ? kNarrowY : kTileY;
+    const int ntiles = ((cfg.W + kTileX - 1) / kTileX) * ((cfg.H + tile_y - 1) / tile_y);
     int tb = 0;
     const int want = cfg.iters_per_launch > 0 ? cfg.iters_per_launch
                                               : auto_tb(cfg.precision, (long long)ntiles * nslots * cfg.C, cfg.H, cfg.W);
-    if (cfg.precision == TVSPEC_PRECISION_F32)
+    if (narrow && cfg.precision == TVSPEC_PRECISION_F32)
+        (void)narrow_tile_kernel<float, float>(want, &tb);
+    else if (narrow)
+        (void)narrow_tile_kernel<double, double>(want, &tb);
+    else if (cfg.precision == TVSPEC_PRECISION_F32)
         (void)tile_kernel<float, float>(want, &tb);
     else
         (void)tile_kernel<double, double>(want, &tb);

@@ -62,6 +62,17 @@ int validate_opts(double tau, int warm, int precision, int ipl)
     return TVSPEC_OK;
 }
 
+int validate_tile_shape(int tile_shape, int solver, int ipl)
+{
+    if (tile_shape != TVSPEC_TILE_SQUARE && tile_shape != TVSPEC_TILE_NARROW)
+        return fail(TVSPEC_EINVAL, "tile_shape must be TVSPEC_TILE_SQUARE or TVSPEC_TILE_NARROW");
+    if (tile_shape == TVSPEC_TILE_NARROW && solver != TVSPEC_SOLVER_CHAMBOLLE)
+        return fail(TVSPEC_EINVAL, "the narrow tile shape is for the Chambolle solver");
+    if (tile_shape == TVSPEC_TILE_NARROW && ipl > 8)
+        return fail(TVSPEC_EINVAL, "the narrow tile shape takes iters_per_launch <= 8");
+    return TVSPEC_OK;
+}
+
 void band_rows_of(const int *edges, int nbands, int *rows)
 {
     rows[0] = 0; // sample 0 carries no phi

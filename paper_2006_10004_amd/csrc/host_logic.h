@@ -32,9 +32,12 @@ inline int fail(int code, const std::string &msg)
 //                   host): 1 <= nb <= K, 0 = e_0 < e_1 < ... < e_nb = K
 //   validate_opts   0 < tau <= 0.25, warm in {0, 1}, a precision mode,
 //                   0 <= iters_per_launch <= 16 (F32) or 8
+//   validate_tile_shape  TVSPEC_TILE_SQUARE or _NARROW; the narrow shape
+//                   only with the Chambolle solver and iters_per_launch <= 8
 int validate_shape(int B, int H, int W, int C, int iters);
 int validate_image(double dt, int K, const int *edges, int nb);
 int validate_opts(double tau, int warm, int precision, int ipl);
+int validate_tile_shape(int tile_shape, int solver, int ipl);
 
 // Round up to a multiple of 256 bytes.
 inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }

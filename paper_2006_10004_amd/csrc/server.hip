@@ -18,20 +18,24 @@
 //       stream); a request whose bucket already runs its cap -- as many
 //       requests as fill the device on their own -- is passed over together
 //       with the later requests of its bucket,
-//   enqueues the next step of every bucket with requests in flight, keeping
-//       at most kDepth steps per bucket ahead of the device, and finalises
-//       (S, checks, report) the requests that step completes.
+//   enqueues the next steps of every bucket with requests in flight -- up to
+//       kMultiStep ROF solves in one graph replay, as many as every request of
+//       the bucket still needs, so none idles inside the replay -- keeping at
+//       most kDepthSteps steps per bucket ahead of the device, and finalises
+//       (S, checks, report) the requests those steps complete.
 // Every device operation of a request is on its bucket's stream, in order,
 // so a slot index or table entry can be reused at the next step boundary;
 // pool memory is only reused once the completion event of its previous owner
 // has fired, since the next owner may be in another bucket.
 //
-// A bucket step is captured once in a hipGraph per (table size, dual-field
-// parity, temporal blocking factor) and replayed; the table size is the
-// high-water mark of occupied slots rounded up, and inactive slots exit at
-// once.  With iters_per_launch = 0 the autotuner times the first kTuneSteps
-// steps of a bucket with each candidate blocking factor (events around the
-// replay) and keeps the fastest; results do not depend on the choice.
+// A run of bucket steps is captured once in a hipGraph per (table size,
+// tile shape, temporal blocking factor, dual-field parity, number of steps)
+// and replayed; the table size is the high-water mark of occupied slots
+// rounded up, and inactive slots exit at once.  With iters_per_launch = 0
+// the autotuner times kTuneSteps single steps of a bucket with each
+// candidate (tile shape, blocking factor) -- 32 x 32 and 32 x 16 tiles,
+// TB 4, 5 and 8 -- (events around the replay) and keeps the fastest;
+// results do not depend on the choice.
 
 #include <hip/hip_runtime.h>
 
@@ -60,7 +64,8 @@ double ms_between(Clock::time_point a, Clock::time_point b)
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-constexpr int kDepth = 3;         // bucket steps enqueued ahead of the device
+constexpr int kDepthSteps = 8;    // bucket steps enqueued ahead of the device
+constexpr int kMultiStep = 4;     // bucket steps per graph replay at most
 constexpr int kFillPerCU = 16;    // workgroups per CU that fill the device (run cap; measured
                                   // 4 and 8 lose ~10% throughput to per-step fixed costs)
 constexpr int kSlotCap = 128;     // slots per bucket table
@@ -94,8 +99,12 @@ struct Chunk {
     bool busy = false;
 };
 
+struct TuneCand {
+    int tile, ipl;
+};
+
 struct TuneSample {
-    int ipl;
+    TuneCand c;
     hipEvent_t a, b;
 };
 
@@ -109,13 +118,16 @@ struct Bucket {
     std::vector<Request *> slots;
     int in_use = 0;
     int parity = 0;
-    std::deque<hipEvent_t> inflight; // one event per enqueued step
+    std::deque<std::pair<hipEvent_t, int>> inflight; // one event per enqueued replay, and its steps
+    int inflight_steps = 0;
     std::vector<hipEvent_t> spare;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    int exec_n = -1, exec_ipl = -1;
+    // graphs of the current (table size, tile shape, blocking factor), per
+    // dual-field parity and number of steps
+    hipGraphExec_t exec[2][kMultiStep + 1] = {};
+    int exec_n = -1, exec_ipl = -1, exec_tile = -1;
     // autotuner
     bool tuning = false, collecting = false;
-    std::vector<int> cand;
+    std::vector<TuneCand> cand;
     int cand_i = 0, cand_steps = 0;
     std::vector<TuneSample> samples;
 };
@@ -145,7 +157,7 @@ struct tvspec_server {
     std::vector<std::unique_ptr<tvspec::Bucket>> buckets;
     std::vector<tvspec::Chunk> chunks;
 
-    unsigned long long n_submitted = 0, n_admitted = 0, n_completed = 0, n_steps = 0, n_graphs = 0;
+    unsigned long long n_submitted = 0, n_admitted = 0, n_completed = 0, n_steps = 0, n_replays = 0, n_graphs = 0;
     int in_flight = 0, max_in_flight = 0;
 };
 
@@ -218,8 +230,13 @@ int bucket_for(tvspec_server *s, const Request &q, int *out)
     HIP_TRY(hipMemsetAsync(b->table, 0, (size_t)b->cap * sizeof(SlotDesc), b->st));
     if (s->ipl == 0) {
         b->tuning = true;
-        b->cand = s->precision == TVSPEC_PRECISION_F32 ? std::vector<int>{4, 8, 16} : std::vector<int>{4, 5, 8};
-        b->cfg.iters_per_launch = b->cand[0];
+        const int big = s->precision == TVSPEC_PRECISION_F32 ? 16 : 5;
+        for (int ipl : {4, big, 8})
+            b->cand.push_back(TuneCand{kTileShapeSquare, ipl});
+        for (int ipl : {4, 5, 8})
+            b->cand.push_back(TuneCand{kTileShapeNarrow, ipl});
+        b->cfg.tile = b->cand[0].tile;
+        b->cfg.iters_per_launch = b->cand[0].ipl;
     }
     s->buckets.push_back(std::move(b));
     *out = (int)s->buckets.size() - 1;
@@ -294,10 +311,11 @@ int try_admit(tvspec_server *s, Request *q, bool *admitted)
 void drop_graphs(Bucket &b)
 {
     for (int p = 0; p < 2; ++p)
-        if (b.exec[p]) {
-            (void)hipGraphExecDestroy(b.exec[p]);
-            b.exec[p] = nullptr;
-        }
+        for (int k = 0; k <= kMultiStep; ++k)
+            if (b.exec[p][k]) {
+                (void)hipGraphExecDestroy(b.exec[p][k]);
+                b.exec[p][k] = nullptr;
+            }
 }
 
 // Pick the autotuner's winner once every timed step has completed.
@@ -309,19 +327,20 @@ int tune_collect(Bucket &b, bool *progressed)
             return TVSPEC_OK;
         HIP_TRY(q);
     }
-    std::map<int, float> best;
+    std::map<std::pair<int, int>, float> best;
     for (const TuneSample &t : b.samples) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
-        auto it = best.find(t.ipl);
+        const std::pair<int, int> key(t.c.tile, t.c.ipl);
+        auto it = best.find(key);
         if (it == best.end() || ms < it->second)
-            best[t.ipl] = ms;
+            best[key] = ms;
     }
-    int pick = b.cand.back();
+    TuneCand pick = b.cand.back();
     float pick_ms = 0.f;
     bool first = true;
-    for (int c : b.cand) {
-        auto it = best.find(c);
+    for (const TuneCand &c : b.cand) {
+        auto it = best.find(std::make_pair(c.tile, c.ipl));
         if (it != best.end() && (first || it->second < pick_ms)) {
             pick = c;
             pick_ms = it->second;
@@ -333,39 +352,50 @@ int tune_collect(Bucket &b, bool *progressed)
         (void)hipEventDestroy(t.b);
     }
     b.samples.clear();
-    b.cfg.iters_per_launch = pick;
+    b.cfg.tile = pick.tile;
+    b.cfg.iters_per_launch = pick.ipl;
     b.collecting = false;
     *progressed = true;
     return TVSPEC_OK;
 }
 
-// Enqueue one step of bucket b and the finalisation of the requests it
-// completes.
+// Enqueue the next steps of bucket b and the finalisation of the requests
+// they complete: one step while the autotuner times candidates, otherwise as
+// many as every request of the bucket still needs, up to kMultiStep, in one
+// replay.
 int step_bucket(tvspec_server *s, Bucket &b)
 {
     int hw = 0;
+    int steps = kMultiStep;
     for (int i = 0; i < b.cap; ++i)
-        if (b.slots[i])
+        if (b.slots[i]) {
             hw = i + 1;
+            steps = std::min(steps, b.slots[i]->steps_left);
+        }
     const int n = std::min(b.cap, (hw + kTableRound - 1) / kTableRound * kTableRound);
     const StepConfig cfg = b.cfg;
     const bool timing = b.tuning;
+    if (timing)
+        steps = 1;
     hipEvent_t ta = nullptr, tb = nullptr;
     if (timing) {
         HIP_TRY(hipEventCreate(&ta));
         HIP_TRY(hipEventCreate(&tb));
     }
     if (s->use_graphs) {
-        if (b.exec_n != n || b.exec_ipl != cfg.iters_per_launch) {
+        if (b.exec_n != n || b.exec_ipl != cfg.iters_per_launch || b.exec_tile != cfg.tile) {
             drop_graphs(b);
             b.exec_n = n;
             b.exec_ipl = cfg.iters_per_launch;
+            b.exec_tile = cfg.tile;
         }
-        hipGraphExec_t &ex = b.exec[b.parity];
+        hipGraphExec_t &ex = b.exec[b.parity][steps];
         if (!ex) {
             HIP_TRY(hipStreamBeginCapture(b.st, hipStreamCaptureModeThreadLocal));
             int par = b.parity;
-            const int rc = engine_step(cfg, b.table, n, &par, b.st, 0);
+            int rc = TVSPEC_OK;
+            for (int k = 0; k < steps && rc == TVSPEC_OK; ++k)
+                rc = engine_step(cfg, b.table, n, &par, b.st, 0);
             hipGraph_t g = nullptr;
             const hipError_t e = hipStreamEndCapture(b.st, &g);
             if (rc != TVSPEC_OK) {
@@ -382,22 +412,24 @@ int step_bucket(tvspec_server *s, Bucket &b)
         if (timing)
             HIP_TRY(hipEventRecord(ta, b.st));
         HIP_TRY(hipGraphLaunch(ex, b.st));
-        b.parity ^= (tile_launches_per_step(cfg, n) & 1);
+        b.parity ^= ((steps * tile_launches_per_step(cfg, n)) & 1);
     } else {
         if (timing)
             HIP_TRY(hipEventRecord(ta, b.st));
-        TVSPEC_TRY(engine_step(cfg, b.table, n, &b.parity, b.st, 0));
+        for (int k = 0; k < steps; ++k)
+            TVSPEC_TRY(engine_step(cfg, b.table, n, &b.parity, b.st, 0));
     }
     if (timing) {
         HIP_TRY(hipEventRecord(tb, b.st));
-        b.samples.push_back(TuneSample{cfg.iters_per_launch, ta, tb});
+        b.samples.push_back(TuneSample{b.cand[b.cand_i], ta, tb});
         if (++b.cand_steps == kTuneSteps) {
             b.cand_steps = 0;
             if (++b.cand_i == (int)b.cand.size()) {
                 b.tuning = false;
                 b.collecting = true;
             } else {
-                b.cfg.iters_per_launch = b.cand[b.cand_i];
+                b.cfg.tile = b.cand[b.cand_i].tile;
+                b.cfg.iters_per_launch = b.cand[b.cand_i].ipl;
             }
         }
     }
@@ -409,12 +441,17 @@ int step_bucket(tvspec_server *s, Bucket &b)
         HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     }
     HIP_TRY(hipEventRecord(ev, b.st));
-    b.inflight.push_back(ev);
-    ++s->n_steps;
+    b.inflight.push_back(std::make_pair(ev, steps));
+    b.inflight_steps += steps;
+    s->n_steps += steps;
+    ++s->n_replays;
 
     for (int i = 0; i < b.cap; ++i) {
         Request *q = b.slots[i];
-        if (!q || --q->steps_left > 0)
+        if (!q)
+            continue;
+        q->steps_left -= steps;
+        if (q->steps_left > 0)
             continue;
         TVSPEC_TRY(engine_finalize(cfg, b.table, i, 1, q->r.K, b.st));
         HIP_TRY(hipEventRecord(q->done, b.st));
@@ -481,16 +518,17 @@ int worker_pass(tvspec_server *s, bool *progressed, bool *busy)
     for (auto &bp : s->buckets) {
         Bucket &b = *bp;
         while (!b.inflight.empty()) {
-            const hipError_t e = hipEventQuery(b.inflight.front());
+            const hipError_t e = hipEventQuery(b.inflight.front().first);
             if (e == hipErrorNotReady)
                 break;
             HIP_TRY(e);
-            b.spare.push_back(b.inflight.front());
+            b.spare.push_back(b.inflight.front().first);
+            b.inflight_steps -= b.inflight.front().second;
             b.inflight.pop_front();
         }
         if (b.collecting)
             TVSPEC_TRY(tune_collect(b, progressed));
-        if (b.in_use > 0 && (int)b.inflight.size() < kDepth) {
+        if (b.in_use > 0 && b.inflight_steps < kDepthSteps) {
             TVSPEC_TRY(step_bucket(s, b));
             *progressed = true;
         }
@@ -668,6 +706,7 @@ extern "C" int tvspec_server_info(tvspec_server *srv, tvspec_server_stats *info)
     info->admitted = srv->n_admitted;
     info->completed = srv->n_completed;
     info->steps = srv->n_steps;
+    info->replays = srv->n_replays;
     info->graph_builds = srv->n_graphs;
     info->buckets = (int)srv->buckets.size();
     info->max_in_flight = srv->max_in_flight;
@@ -698,8 +737,8 @@ extern "C" int tvspec_server_destroy(tvspec_server *srv)
         if (b.st && hipStreamSynchronize(b.st) != hipSuccess)
             rc = fail(TVSPEC_EDEVICE, "server destroy: stream synchronisation failed");
         drop_graphs(b);
-        for (hipEvent_t e : b.inflight)
-            (void)hipEventDestroy(e);
+        for (const auto &e : b.inflight)
+            (void)hipEventDestroy(e.first);
         for (hipEvent_t e : b.spare)
             (void)hipEventDestroy(e);
         for (const TuneSample &t : b.samples) {

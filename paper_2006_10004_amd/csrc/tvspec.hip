@@ -164,6 +164,7 @@ struct Batch {
     hipStream_t st;
     int solver = kSolverChambolle;
     double sigma = 0.0;
+    int tile = kTileShapeSquare;
 };
 
 // The slot descriptor and band edges of an allocation-free call, passed by
@@ -272,6 +273,7 @@ int run_batch(const Batch &a)
     StepConfig cfg{a.H, a.W, a.C, a.iters, a.tau, a.warm, a.ipl, a.precision};
     cfg.solver = a.solver;
     cfg.sigma = a.sigma;
+    cfg.tile = a.tile;
     TVSPEC_TRY(engine_init(cfg, d_table, 0, a.B, a.st));
     int parity = 0;
     for (int s = 0; s <= Kmax; ++s) {
@@ -425,6 +427,7 @@ extern "C" void tvspec_default_options(tvspec_options *o)
     o->iters_per_launch = 0;
     o->device_ptrs = 0;
     o->stream = nullptr;
+    o->tile_shape = TVSPEC_TILE_SQUARE;
 }
 
 namespace {
@@ -478,6 +481,7 @@ extern "C" int tvspec_decompose_ex(const tvspec_args *args, const tvspec_options
     } else {
         return fail(TVSPEC_EINVAL, "solver must be TVSPEC_SOLVER_CHAMBOLLE or TVSPEC_SOLVER_PDHG");
     }
+    TVSPEC_TRY(validate_tile_shape(o.tile_shape, o.solver, o.iters_per_launch));
     const size_t n_all = (size_t)x.H * x.W * x.C;
     if (!o.device_ptrs)
         for (size_t q = 0; q < n_all; ++q)
@@ -509,6 +513,7 @@ extern "C" int tvspec_decompose_ex(const tvspec_args *args, const tvspec_options
     a.precision = o.precision;
     a.solver = solver;
     a.sigma = solver == kSolverPDHG ? sigma : 0.0;
+    a.tile = o.tile_shape == TVSPEC_TILE_NARROW ? kTileShapeNarrow : kTileShapeSquare;
     HostIO &h = g_hostio[dev];
     if (o.device_ptrs) {
         a.f = x.f;

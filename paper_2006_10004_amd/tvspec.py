@@ -73,7 +73,7 @@ class _Result(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_ulonglong), ("admitted", ctypes.c_ulonglong),
                 ("completed", ctypes.c_ulonglong), ("steps", ctypes.c_ulonglong),
-                ("graph_builds", ctypes.c_ulonglong), ("buckets", ctypes.c_int),
+                ("replays", ctypes.c_ulonglong), ("graph_builds", ctypes.c_ulonglong), ("buckets", ctypes.c_int),
                 ("max_in_flight", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
                 ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
@@ -89,7 +89,7 @@ class _Args(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("warm_start", ctypes.c_int), ("precision", ctypes.c_int), ("iters_per_launch", ctypes.c_int),
-                ("device_ptrs", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("device_ptrs", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_shape", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
@@ -100,6 +100,9 @@ class _Report(ctypes.Structure):
 TVSPEC_SOLVER_CHAMBOLLE = 0
 TVSPEC_SOLVER_PDHG = 1
 SOLVERS = {"chambolle": TVSPEC_SOLVER_CHAMBOLLE, "pdhg": TVSPEC_SOLVER_PDHG}
+TVSPEC_TILE_SQUARE = 0
+TVSPEC_TILE_NARROW = 1
+TILE_SHAPES = {"square": TVSPEC_TILE_SQUARE, "narrow": TVSPEC_TILE_NARROW}
 
 
 class TvspecError(RuntimeError):
@@ -341,9 +344,12 @@ def tvspec_default_options() -> dict:
 def tvspec_decompose_ex(f, dt: float, K: int, inner_iters: int, band_edges, solver: str = "chambolle",
                         tau: float = 0.0, sigma: float = 0.0, warm_start: bool = False,
                         precision: str = DEFAULT_PRECISION, iters_per_launch: int = 0,
-                        stream: torch.cuda.Stream | None = None, report: bool = True, out: dict | None = None):
+                        stream: torch.cuda.Stream | None = None, report: bool = True, out: dict | None = None,
+                        tile_shape: str = "square"):
     """tvspec_decompose_ex: f is a (C,H,W)/(H,W) float32 numpy array (host
-    buffers, synchronous) or GPU tensor (device buffers on `stream`).
+    buffers, synchronous) or GPU tensor (device buffers on `stream`);
+    tile_shape "square" (32 x 32) or "narrow" (32 x 16) for the Chambolle
+    tile kernel.
 
     Returns (outputs, report): outputs as tvspec_decompose (numpy) or
     tvspec_decompose_dev (tensors, with stats); report a dict of recon_err,
@@ -358,6 +364,7 @@ def tvspec_decompose_ex(f, dt: float, K: int, inner_iters: int, band_edges, solv
     o.warm_start = 1 if warm_start else 0
     o.precision = PRECISIONS[precision]
     o.iters_per_launch = int(iters_per_launch)
+    o.tile_shape = TILE_SHAPES[tile_shape]
     if isinstance(f, torch.Tensor):
         if not f.is_cuda or f.dtype != torch.float32:
             raise TypeError("a tensor f must be a float32 GPU tensor")

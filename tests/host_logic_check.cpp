@@ -68,6 +68,11 @@ static void check_validation()
     CHECK(validate_opts(0.2500001, 0, TVSPEC_PRECISION_F32, 0) == TVSPEC_EINVAL);
     CHECK(validate_opts(0.0, 0, TVSPEC_PRECISION_F32, 0) == TVSPEC_EINVAL);
     CHECK(validate_opts(nan, 0, TVSPEC_PRECISION_F32, 0) == TVSPEC_EINVAL);
+    CHECK(validate_tile_shape(TVSPEC_TILE_SQUARE, TVSPEC_SOLVER_PDHG, 16) == TVSPEC_OK);
+    CHECK(validate_tile_shape(TVSPEC_TILE_NARROW, TVSPEC_SOLVER_CHAMBOLLE, 8) == TVSPEC_OK);
+    CHECK(validate_tile_shape(TVSPEC_TILE_NARROW, TVSPEC_SOLVER_CHAMBOLLE, 16) == TVSPEC_EINVAL);
+    CHECK(validate_tile_shape(TVSPEC_TILE_NARROW, TVSPEC_SOLVER_PDHG, 0) == TVSPEC_EINVAL);
+    CHECK(validate_tile_shape(2, TVSPEC_SOLVER_CHAMBOLLE, 0) == TVSPEC_EINVAL);
     CHECK(validate_opts(0.1, 2, TVSPEC_PRECISION_F32, 0) == TVSPEC_EINVAL);
     CHECK(validate_opts(0.1, 0, 3, 0) == TVSPEC_EINVAL);
     CHECK(validate_opts(0.1, 0, TVSPEC_PRECISION_F64, 9) == TVSPEC_EINVAL);

@@ -224,13 +224,15 @@ def test_ex_default_options(tv):
     o = tv.tvspec_default_options()
     assert o["solver"] == tv.TVSPEC_SOLVER_CHAMBOLLE and o["tau"] == 0.0 and o["warm_start"] == 0
     assert o["precision"] == tv.TVSPEC_PRECISION_MIXED and o["device_ptrs"] == 0 and o["stream"] is None
+    assert o["tile_shape"] == tv.TVSPEC_TILE_SQUARE
 
 
 EX_BAD = [
     (dict(solver=2), "solver"), (dict(device_ptrs=2), "device_ptrs"), (dict(tau=0.3), "tau"),
     (dict(solver=1, tau=0.5, sigma=0.5), "PDHG"), (dict(precision=4), "precision"),
     (dict(iters_per_launch=9), "iters_per_launch"), (dict(H=1), "H and W"), (dict(K=0), "K"),
-    (dict(device_ptrs=1, stats=None), "null"), (dict(f=None), "null"),
+    (dict(device_ptrs=1, stats=None), "null"), (dict(f=None), "null"), (dict(tile_shape=2), "tile_shape"),
+    (dict(tile_shape=1, solver=1), "narrow"), (dict(tile_shape=1, precision=0, iters_per_launch=16), "narrow"),
 ]
 
 

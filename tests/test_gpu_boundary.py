@@ -56,6 +56,20 @@ def test_ex_device_report(tv, orc):
     assert np.abs(g["residual"] - r["residual"]).max() <= 2e-4
 
 
+@pytest.mark.parametrize("precision,ipl", [("mixed", 0), ("mixed", 4), ("mixed", 5), ("mixed", 8), ("mixed", 3),
+                                           ("f64", 0), ("f32", 8)])
+def test_ex_narrow_tiles_equal_square(tv, precision, ipl):
+    """The 32 x 16 tile shape gives the 32 x 32 shape's results bit for bit
+    (same per-pixel arithmetic), on a ragged 3-channel image: rows 70 = 4 x
+    16 + 6, columns 45 = 32 + 13."""
+    f = synth.shapes_image(synth.ShapeSpec(70, 45, 3, 6), seed=8)
+    ref = reference(tv, f, precision=precision, iters_per_launch=ipl)
+    ft = torch.from_numpy(f).cuda()
+    out, _ = tv.tvspec_decompose_ex(ft, CFG["dt"], CFG["K"], CFG["iters"], CFG["edges"], precision=precision,
+                                    iters_per_launch=ipl, tile_shape="narrow")
+    assert_same(to_np(out), ref)
+
+
 def test_ex_host_buffers_and_pdhg(tv):
     f = synth.shapes_image(synth.ShapeSpec(64, 72, 2, 6), seed=6)
     ref = reference(tv, f)

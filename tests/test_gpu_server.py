@@ -130,6 +130,35 @@ def test_options_equal_direct(tv, opts):
         assert_same(mix[i], ref[i])
 
 
+def test_tuned_multistep_replays_equal_direct(tv):
+    """Flows long enough for the autotuner to time every (tile shape,
+    blocking factor) candidate and then run several ROF solves per graph
+    replay, with requests of different K sharing a bucket (so replays shrink
+    to what the shortest request still needs): results equal the direct
+    path's bit for bit."""
+    dev = torch.device("cuda:0")
+    cases = [(1, 64, 64, 0.005, 41, 30, [0, 1, 2, 4, 41]), (1, 64, 64, 0.004, 27, 30, [0, 3, 27]),
+             (3, 48, 80, 0.005, 33, 20, [0, 1, 33])]
+    fs = [torch.from_numpy(image(C, H, W, 300 + i)).to(dev) for i, (C, H, W, *_r) in enumerate(cases)]
+    ref = [tv.tvspec_decompose_dev(f, dt, K, it, e) for f, (C, H, W, dt, K, it, e) in zip(fs, cases)]
+    torch.cuda.synchronize()
+    with tv.Server(1 << 30) as srv:
+        ts, outs = [], []
+        for f, (C, H, W, dt, K, it, e) in zip(fs, cases):
+            t, o = srv.submit(f, dt, K, it, e)
+            ts.append(t)
+            outs.append(o)
+        wait_all(srv, ts)
+        info = srv.info()
+    for a, b in zip(outs, ref):
+        assert_same(a, b)
+    # the two 64 x 64 requests share their bucket's 42 steps (more if the
+    # second joins late); the other bucket takes 34; after each bucket's 18
+    # timed single steps come runs of up to 4
+    assert info["steps"] >= 42 + 34, info
+    assert info["replays"] <= info["steps"] - 20, info
+
+
 def test_budget_limits_admission(tv):
     """A pool that holds little more than the largest request's working
     state: admission waits for memory to free up, the pool's peak stays
