@@ -277,12 +277,13 @@ PAPER_1024_CONTEXT = {"hardware": "NVIDIA Quadro P6000", "pixels": 1048576, "mod
                       "speedup_tvspecnet": 28.2811 / 0.0020, "speedup_u_tvspecnet": 28.2811 / 0.0062}
 
 
-def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_sides=(1024, 2048), mega_requests=8,
+def surrogate_block(n_train, steps, test_images=64, batch=16, lr=3e-3, mega_sides=(1024, 2048), mega_requests=8,
                     seed=11):
     """The learned surrogate end to end on the surrogate workload: training
     data decomposed by the batched plain path (3 x 256^2 shape images,
     dt 0.005, K 100, 150 iterations, 4 dyadic bands), `steps` Adam steps
-    (batch 16, lr 1e-3), band errors on held-out images, inference
+    (batch 16, learning rate: 500 warm-up steps to `lr`, then cosine decay to
+    1e-5), band errors on held-out images, inference
     throughput against the bf16 MFMA peak, serving with identity-error
     fallback; then megapixel serving: `mega_requests` images alternating
     over mega_sides (300 shapes, radius up to 400 px), one request at a time,
@@ -296,7 +297,8 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     rec = {"workload": "3x256x256 synthetic shape images (half 40-shape images, half crops of 1024x1024 "
                        "300-shape images), encoder-decoder 48-96-192-384, 4 bands x 3 + residual; "
                        "targets from the plain path dt 0.005, K 100, 150 iterations",
-           "train_images": n_train, "test_images": test_images, "steps": steps, "batch": batch, "lr": lr}
+           "train_images": n_train, "test_images": test_images, "steps": steps, "batch": batch, "lr": lr,
+           "lr_schedule": "linear warm-up over %d steps to lr, cosine decay to %g" % (S.LR_WARMUP, S.LR_FLOOR)}
     t0 = time.perf_counter()
     imgs = np.concatenate([S.make_training_images(n_train, 256, 20000 + seed),
                            S.make_training_images(test_images, 256, 90000 + seed)])
@@ -315,7 +317,8 @@ def surrogate_block(n_train, steps, test_images=64, batch=16, lr=1e-3, mega_side
     losses = []
     t1 = time.perf_counter()
     for a in range(0, steps, 250):
-        losses += S.train(net, ftr, btr, rtr, min(250, steps - a), batch, lr, seed=seed + a)
+        losses += S.train(net, ftr, btr, rtr, min(250, steps - a), batch,
+                          lambda i, a=a: S.cosine_lr(a + i, steps, peak=lr), seed=seed + a)
         print("bench: surrogate step %d loss %.4f" % (len(losses), float(np.mean(losses[-25:]))), file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
@@ -653,7 +656,7 @@ def main():
                     help="also time this many decompositions with the primal-dual solver (0 = skip)")
     ap.add_argument("--sur-train-images", type=int, default=8192,
                     help="training images of the learned surrogate (0 = skip the surrogate)")
-    ap.add_argument("--sur-steps", type=int, default=6000, help="Adam steps of the surrogate's training")
+    ap.add_argument("--sur-steps", type=int, default=16000, help="Adam steps of the surrogate's training")
     ap.add_argument("--sur-forward-only", type=int, default=0, metavar="N",
                     help="instead of the benchmark, time N forward passes of the surrogate network "
                          "(batch 16 of 3x256x256) and print that record")

@@ -135,14 +135,34 @@ struct ConvShape {
     static constexpr int kItemsPerThread = (kItems + kThreads - 1) / kThreads;
 };
 
+// Optional output form of the network's last layer:
+//   planar  the last layer (float32 output, one block of 16 channels)
+//           writes the planar output [B][15][H][W] directly: bands as
+//           computed, the residual channels 12..14 plus fout (f), and with
+//           ipart the partial sums over each 8 x 32 tile, ipart[b][tile], of
+//           |f - sum_j band_j - residual| over the 3 channels, taken on the
+//           stored outputs (the reconstruction identity, Eq. (7)).
+struct ConvIO {
+    float *planar = nullptr;
+    const float *fout = nullptr;
+    double *ipart = nullptr;
+};
+
+// Waves per SIMD the last layer's shape keeps with its planar epilogue
+// (which would otherwise cost it one: 5 -> 4).
+template <bool F32OUT, int NF, int CC> constexpr int conv_min_waves()
+{
+    return (F32OUT && NF == 1 && CC == 16) ? 5 : 1;
+}
+
 template <bool F32OUT, int NF, int CC, int WAVES, int RPW>
-__global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
+__global__ __launch_bounds__(64 * WAVES, (conv_min_waves<F32OUT, NF, CC>())) void k_conv3x3(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wt,
                                                         const float *__restrict__ bias,
                                                         const __bf16 *__restrict__ mask,
                                                         const float *__restrict__ oscale, void *__restrict__ Y, int B,
                                                         int H, int W, int Cin, int Cout, int relu, int tiles_x,
                                                         int tiles_y, const __bf16 *__restrict__ Xlow, int Clow,
-                                                        __bf16 *__restrict__ Ypool)
+                                                        __bf16 *__restrict__ Ypool, ConvIO io)
 {
     using CS = ConvShape<CC, WAVES, RPW>;
     constexpr int kRF = 2 * RPW;  // 16-pixel row fragments per wave
@@ -165,7 +185,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     constexpr int kNB = kPD + 1;                   // rotating weight buffers
     static_assert(kPD == 2 || kPD == 3, "prefetch distance 2 or 3");
     static_assert(CS::kSteps >= kPD, "the prologue's steps lie in the first chunk");
-    constexpr int kTileBytes = F32OUT ? 0 : kTilePix * kOPitch;
+    constexpr int kPlanarPitch = 80;               // planar epilogue: 16 floats + 16 bytes per pixel
+    constexpr int kTileBytes = F32OUT ? (NF == 1 ? kTilePix * kPlanarPitch : 0) : kTilePix * kOPitch;
     constexpr int kSmem = (kXBytes + kNB * kBBytes > kTileBytes) ? kXBytes + kNB * kBBytes : kTileBytes;
     // input chunk and the weight buffers; after the last step, the
     // epilogue's output tile (bf16 outputs) in the same memory
@@ -371,6 +392,74 @@ __global__ __launch_bounds__(64 * WAVES) void k_conv3x3(const __bf16 *__restrict
     // float32 outputs (the network's last layer: 15 channels, 60-byte pixels)
     // are stored directly, element by element: staging them costs that
     // kernel an occupancy step and saves nothing measurable.
+    if constexpr (F32OUT && NF == 1) {
+        if (io.planar) {
+            // stage the tile [pixel][16 channels] (the last step's barrier
+            // ended every read of the staging buffers), then one thread per
+            // pixel: planar stores, residual = channel + f, identity term
+#pragma unroll
+            for (int r = 0; r < kRF; ++r) {
+                const int ly = RPW * wave + (r >> 1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lx = 16 * (r & 1) + 4 * g + i;
+                    float v = acc[r][0][i] + (bias && r16 < Cout ? bias[r16] : 0.f);
+                    if (relu)
+                        v = v > 0.f ? v : 0.f;
+                    if (oscale && r16 < Cout)
+                        v *= oscale[r16];
+                    *(float *)(smem + (ly * kTileX + lx) * kPlanarPitch + 4 * r16) = v;
+                }
+            }
+            __syncthreads();
+            __shared__ double s_red[WAVES];
+            double sum = 0.0;
+            const size_t HWs = (size_t)H * W;
+            for (int pix = threadIdx.x; pix < kTilePix; pix += kNT) {
+                const int ly = pix / kTileX;
+                const int yy = y0 + ly;
+                const int xx = x0 + pix - ly * kTileX;
+                if (yy >= H || xx >= W)
+                    continue;
+                const size_t q = (size_t)yy * W + xx;
+                const float *t = (const float *)(smem + pix * kPlanarPitch);
+                float v[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    v[k] = t[k];
+                float *ob = io.planar + (size_t)b * 15 * HWs + q;
+#pragma unroll
+                for (int c = 0; c < 12; ++c)
+                    ob[(size_t)c * HWs] = v[c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float fc = io.fout[((size_t)b * 3 + c) * HWs + q];
+                    const float rc = v[12 + c] + fc;
+                    ob[(size_t)(12 + c) * HWs] = rc;
+                    float d = fc;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        d -= v[3 * j + c];
+                    d -= rc;
+                    sum += fabsf(d);
+                }
+            }
+            if (io.ipart) {
+                for (int off = 32; off > 0; off >>= 1)
+                    sum += __shfl_xor(sum, off, 64);
+                if (lane == 0)
+                    s_red[wave] = sum;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double tot = s_red[0];
+                    for (int w = 1; w < WAVES; ++w)
+                        tot += s_red[w];
+                    io.ipart[tile] = tot;
+                }
+            }
+            return;
+        }
+    }
     if constexpr (F32OUT) {
 #pragma unroll
         for (int c = 0; c < NF; ++c) {
@@ -985,54 +1074,6 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh)
     return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// o [P][16] float -> out [B][15][H][W], the residual channels plus f
-// [B][3][H][W].  One thread per pixel (its 16 values are one 64-byte row of
-// o).  With part != nullptr the block also writes part[b][blockIdx.x], the
-// sum over its pixels and the 3 channels of |f - sum_j band_j - residual|
-// taken on the stored outputs (the reconstruction identity, Eq. (7)).
-// Grid (blocks per image, B).
-__global__ __launch_bounds__(kT) void k_unpack_output(const float *__restrict__ o, const float *__restrict__ f,
-                                                      float *__restrict__ out, long long HW,
-                                                      double *__restrict__ part)
-{
-    __shared__ double sh[kT / 64];
-    const int b = blockIdx.y;
-    double acc = 0.0;
-    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < HW; q += (long long)gridDim.x * kT) {
-        const float4 *op = (const float4 *)(o + (size_t)(b * HW + q) * kOutPad);
-        float v[kOutPad];
-#pragma unroll
-        for (int k = 0; k < kOutPad / 4; ++k) {
-            const float4 t = op[k];
-            v[4 * k] = t.x;
-            v[4 * k + 1] = t.y;
-            v[4 * k + 2] = t.z;
-            v[4 * k + 3] = t.w;
-        }
-        float *ob = out + (size_t)b * kOutC * HW + q;
-#pragma unroll
-        for (int c = 0; c < 3 * TVSPEC_NET_BANDS; ++c)
-            ob[(size_t)c * HW] = v[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float fc = f[((size_t)b * 3 + c) * HW + q];
-            const float rc = v[3 * TVSPEC_NET_BANDS + c] + fc;
-            ob[(size_t)(3 * TVSPEC_NET_BANDS + c) * HW] = rc;
-            float d = fc;
-#pragma unroll
-            for (int j = 0; j < TVSPEC_NET_BANDS; ++j)
-                d -= v[3 * j + c];
-            d -= rc;
-            acc += fabsf(d);
-        }
-    }
-    if (part) {
-        const double t = block_sum_d(acc, sh);
-        if (threadIdx.x == 0)
-            part[(size_t)b * gridDim.x + blockIdx.x] = t;
-    }
-}
-
 // err[b] = (sum of part[b][0..nblk) in order) / (3 HW).
 __global__ __launch_bounds__(kT) void k_identity_total(const double *__restrict__ part, int B, int nblk, long long HW,
                                                        float *__restrict__ err)
@@ -1310,7 +1351,7 @@ int ensure(void **p, size_t *have, size_t bytes)
 template <int NF, int CC, int WAVES, int RPW>
 void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                    int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                   const __bf16 *xlow, int clow, __bf16 *ypool)
+                   const __bf16 *xlow, int clow, __bf16 *ypool, const ConvIO &io)
 {
     const int tiles_x = (W + kTileX - 1) / kTileX;
     constexpr int kTileY = RPW * WAVES;
@@ -1318,10 +1359,10 @@ void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *
     const dim3 grid((unsigned)((long long)tiles_x * tiles_y * B), (unsigned)((Cout + NF * 16 - 1) / (NF * 16)));
     if (f32)
         hipLaunchKernelGGL((k_conv3x3<true, NF, CC, WAVES, RPW>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask, oscale,
-                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, nullptr);
+                           y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, nullptr, io);
     else
         hipLaunchKernelGGL((k_conv3x3<false, NF, CC, WAVES, RPW>), grid, dim3(64 * WAVES), 0, st, x, w, bias, mask,
-                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, ypool);
+                           oscale, y, B, H, W, Cin, Cout, relu, tiles_x, tiles_y, xlow, clow, ypool, io);
 }
 
 // Four waves per workgroup, two output rows per wave (8 x 32 pixel tiles):
@@ -1332,9 +1373,10 @@ void conv_launch_w(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *
 template <int NF, int CC>
 void conv_launch(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout,
                  int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                 const __bf16 *xlow, int clow, __bf16 *ypool)
+                 const __bf16 *xlow, int clow, __bf16 *ypool, const ConvIO &io)
 {
-    conv_launch_w<NF, CC, 4, 2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool);
+    conv_launch_w<NF, CC, 4, 2>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool,
+                                io);
 }
 
 // Column fragments per wave (NF) and input channels per LDS chunk (CC),
@@ -1372,12 +1414,12 @@ void conv_shape(int B, int H, int W, int Cin, int Cout, int *nf, int *cc)
 template <int NF>
 void conv_launch_cc(int cc, const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias,
                     int Cout, int relu, const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale,
-                    const __bf16 *xlow, int clow, __bf16 *ypool)
+                    const __bf16 *xlow, int clow, __bf16 *ypool, const ConvIO &io)
 {
     switch (cc) {
-    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
-    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
-    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool); break;
+    case 32: conv_launch<NF, 32>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool, io); break;
+    case 16: conv_launch<NF, 16>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool, io); break;
+    default: conv_launch<NF, 8>(x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, ypool, io); break;
     }
 }
 
@@ -1390,10 +1432,12 @@ void conv_launch_cc(int cc, const __bf16 *x, int B, int H, int W, int Cin, const
 // else by k_maxpool afterwards; the values are the same either way.
 int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, const float *bias, int Cout, int relu,
              const __bf16 *mask, void *y, bool f32, hipStream_t st, const float *oscale = nullptr,
-             const __bf16 *xlow = nullptr, int clow = 0, __bf16 *ypool = nullptr)
+             const __bf16 *xlow = nullptr, int clow = 0, __bf16 *ypool = nullptr, const ConvIO &io = ConvIO())
 {
     int nf = 1, cc = 8;
     conv_shape(B, H, W, Cin, Cout, &nf, &cc);
+    if (io.planar && (!f32 || Cout != 16 || nf != 1 || !io.fout))
+        return fail(TVSPEC_EINVAL, "planar network output: the last layer's shape only");
     if (xlow && (clow <= 0 || clow >= Cin || clow % cc != 0 || (Cin - clow) % 8 != 0 || H % 2 || W % 2))
         return fail(TVSPEC_EINVAL, "fused concatenation: chunk width must divide the low-resolution channels");
     if (ypool && (H % 2 || W % 2 || f32 || Cout % 8))
@@ -1402,11 +1446,11 @@ int conv_fwd(const __bf16 *x, int B, int H, int W, int Cin, const __bf16 *w, con
                            ((uintptr_t)ypool & 15) == 0;
     __bf16 *yp = fuse_pool ? ypool : nullptr;
     switch (nf) {
-    case 1: conv_launch_cc<1>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
-    case 2: conv_launch_cc<2>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
-    case 3: conv_launch_cc<3>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
-    case 4: conv_launch_cc<4>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
-    default: conv_launch_cc<6>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp); break;
+    case 1: conv_launch_cc<1>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp, io); break;
+    case 2: conv_launch_cc<2>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp, io); break;
+    case 3: conv_launch_cc<3>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp, io); break;
+    case 4: conv_launch_cc<4>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp, io); break;
+    default: conv_launch_cc<6>(cc, x, B, H, W, Cin, w, bias, Cout, relu, mask, y, f32, st, oscale, xlow, clow, yp, io); break;
     }
     if (ypool && !fuse_pool) {
         const long long cnt = (long long)B * (H / 2) * (W / 2) * (Cout / 8);
@@ -1556,9 +1600,10 @@ struct tvspec_net {
     float *tgt = nullptr;     // [P][16]
     __bf16 *dout = nullptr;   // [P][16]
     float *lpart = nullptr, *nd = nullptr, *loss = nullptr;
-    double *ipart = nullptr;  // [max_batch][lblk] identity-error partials
+    double *ipart = nullptr;  // [max_batch][otiles] identity-error partials
     float *oscale = nullptr;  // [16] output channel scales (1 by default)
     int lblk = 0;
+    int otiles = 0;           // 8 x 32 output tiles per image (identity partials of the forward pass)
     tvspec::nn::Work wk;
     std::vector<void *> allocs;
     std::mutex mu;
@@ -1607,9 +1652,13 @@ int requant_all(tvspec_net *n, hipStream_t st)
 }
 
 // training: materialise the decoder's concatenations (the weight gradients
-// read them); otherwise the first decoder convolution of each level reads
-// the upsampled lower level and the skip tensor in place.
-int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training)
+// read them) and leave the output in n->out ([P][16]); otherwise the first
+// decoder convolution of each level reads the upsampled lower level and the
+// skip tensor in place, and the last layer writes the planar output
+// `planar` (with the identity partials into ipart[b][tile] unless ipart is
+// null).
+int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training, float *planar = nullptr,
+            double *ipart = nullptr)
 {
     Act *A = n->A;
     const int H = n->H, W = n->W;
@@ -1654,8 +1703,14 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training)
     TVSPEC_TRY(up_conv(D2B, E1B, C1, 12, D1A));
     TVSPEC_TRY(conv(13, D1A, D1B));
     const Layer &lo = n->L[14];
+    ConvIO io;
+    if (!training && planar) {
+        io.planar = planar;
+        io.fout = f;
+        io.ipart = ipart;
+    }
     TVSPEC_TRY(conv_fwd(A[D1B].a, B, H, W, lo.cin, lo.wq, lo.bias, lo.cout, 0, nullptr, n->out, true, st,
-                        n->oscale));
+                        n->oscale, nullptr, 0, nullptr, io));
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1866,6 +1921,7 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
     }
     const size_t P = (size_t)max_batch * H * W;
     n->lblk = (int)std::min<long long>(1024, ((long long)H * W + kT - 1) / kT);
+    n->otiles = ((H + 7) / 8) * ((W + kTileX - 1) / kTileX);
     int rc = net_alloc(n, (void **)&n->out, P * kOutPad * sizeof(float));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->tgt, P * kOutPad * sizeof(float));
@@ -1876,7 +1932,7 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->nd, (size_t)max_batch * kGroups * 2 * sizeof(float));
     if (rc == TVSPEC_OK)
-        rc = net_alloc(n, (void **)&n->ipart, (size_t)max_batch * n->lblk * sizeof(double));
+        rc = net_alloc(n, (void **)&n->ipart, (size_t)max_batch * n->otiles * sizeof(double));
     if (rc == TVSPEC_OK)
         rc = net_alloc(n, (void **)&n->gpart, kNormBlocks * sizeof(double));
     if (rc == TVSPEC_OK)
@@ -2023,12 +2079,10 @@ extern "C" int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B
     TVSPEC_TRY(check_batch(net, B));
     std::lock_guard<std::mutex> lock(net->mu);
     hipStream_t st = (hipStream_t)stream;
-    TVSPEC_TRY(forward(net, f, B, st, false));
+    TVSPEC_TRY(forward(net, f, B, st, false, out, err ? net->ipart : nullptr));
     const long long HW = (long long)net->H * net->W;
-    hipLaunchKernelGGL(k_unpack_output, dim3(net->lblk, B), dim3(kT), 0, st, net->out, f, out, HW,
-                       err ? net->ipart : nullptr);
     if (err)
-        hipLaunchKernelGGL(k_identity_total, dim3(1), dim3(kT), 0, st, net->ipart, B, net->lblk, HW, err);
+        hipLaunchKernelGGL(k_identity_total, dim3(1), dim3(kT), 0, st, net->ipart, B, net->otiles, HW, err);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }

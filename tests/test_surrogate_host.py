@@ -57,3 +57,18 @@ def test_conv_flops_of_the_encoder_decoder():
         total += 2 * 9 * ci * co * (256 >> lvl) ** 2
     assert S.conv_flops(256, 256) == total
     assert abs(total / 1e9 - 48.58) < 0.01
+
+
+def test_cosine_lr_schedule():
+    """Linear warm-up to the peak, then cosine decay that reaches the floor
+    at the last step and never rises."""
+    from paper_2006_10004_amd import surrogate as S
+    steps, peak, warm, floor = 1000, 3e-3, 100, 1e-5
+    lr = [S.cosine_lr(i, steps, peak, warm, floor) for i in range(steps + 1)]
+    assert abs(lr[0] - peak / warm) < 1e-15 and abs(lr[warm - 1] - peak) < 1e-15
+    assert all(abs(lr[i] - peak * (i + 1) / warm) < 1e-15 for i in range(warm))
+    assert abs(lr[warm] - peak) < 1e-15
+    assert abs(lr[steps] - floor) < 1e-15
+    mid = warm + (steps - warm) // 2
+    assert abs(lr[mid] - (floor + 0.5 * (peak - floor))) < 1e-12
+    assert all(lr[i + 1] <= lr[i] + 1e-18 for i in range(warm, steps))
