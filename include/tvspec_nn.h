@@ -178,10 +178,20 @@ TVSPEC_API int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B
  * the residual's learned part has to carry; floor_j is set by
  * tvspec_net_set_loss_floor (0 by default).  A group with a zero
  * denominator contributes 0.
- * *loss (host) receives the batch loss; the call waits for the stream.
+ * *loss (host) receives the batch loss; the call then waits for the
+ * stream.  With loss = NULL the step is only enqueued on the stream (the
+ * caller may prepare the next batch meanwhile); tvspec_net_last_loss reads
+ * the latest step's loss later.
  */
 TVSPEC_API int tvspec_net_train_step(tvspec_net *net, const float *f, const double *bands,
                                      const double *residual, int B, float lr, float *loss, void *stream);
+
+/*
+ * The loss of the latest training step or loss evaluation on this network:
+ * waits for `stream` (where that step was enqueued), then copies it to
+ * *loss (host).
+ */
+TVSPEC_API int tvspec_net_last_loss(tvspec_net *net, float *loss, void *stream);
 
 /*
  * The loss and the parameter gradients of a batch without an update

@@ -666,7 +666,7 @@ __device__ __forceinline__ bf16x8 tr_operand(const lds_u8 *p, int half)
 
 template <int OW, int WC>
 __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
-                                                   float *__restrict__ part, float *__restrict__ bpart, int H, int W,
+                                                   float *__restrict__ part, size_t rs, int with_bias, int H, int W,
                                                    int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles,
                                                    int tpr)
 {
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__
     const int t0 = s * tpr;
     const int t1 = min(tiles, t0 + tpr);
     const int K = 9 * Cin;
-    const bool do_bias = bpart != nullptr && ct == 0 && wave == 0;
+    const bool do_bias = with_bias && ct == 0 && wave == 0;
 
     floatx4 acc[OW][9];
     floatx4 bacc[OW];
@@ -816,7 +816,9 @@ __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__
 
     // result lane layout: column r16 (input channel), rows 4 g .. 4 g + 3
     // (output channels) of each fragment
-    float *const out = part + (size_t)s * Cout * K;
+    // range s's row of the partial sums: the weight gradient [o][tap][c],
+    // then (with_bias) the bias gradient [o]
+    float *const out = part + (size_t)s * rs;
     const int c = c0 + 16 * wave + r16;
     if (c < Cin) {
 #pragma unroll
@@ -838,7 +840,7 @@ __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__
             for (int i = 0; i < 4; ++i) {
                 const int o = o0 + 16 * f + 4 * g + i;
                 if (o < Cout)
-                    bpart[(size_t)s * Cout + o] = bacc[f][i];
+                    out[(size_t)Cout * K + o] = bacc[f][i];
             }
     }
 }
@@ -873,8 +875,40 @@ __global__ __launch_bounds__(kT) void k_reduce_groups(float *__restrict__ part, 
     }
 }
 
+// Where stage 2 puts column q of a weight-gradient row ([cout][9][cin], then
+// the bias [cout]): into dw / db as they are, or into a layer's slice of the
+// flat parameter gradient (weights [cout_r][9][cin_r] then bias [cout_r],
+// the padding channels dropped).
+struct RowOut {
+    float *dw = nullptr, *db = nullptr, *flat = nullptr;
+    size_t nw = 0;  // weight columns (cout 9 cin)
+    int cin = 0, cin_r = 0, cout_r = 0;
+};
+
+__device__ __forceinline__ void put_col(const RowOut &w, size_t q, float v)
+{
+    if (!w.flat) {
+        if (q < w.nw)
+            w.dw[q] = v;
+        else
+            w.db[q - w.nw] = v;
+        return;
+    }
+    if (q < w.nw) {
+        const int c = (int)(q % w.cin);
+        const int tap = (int)((q / w.cin) % 9);
+        const int o = (int)(q / ((size_t)9 * w.cin));
+        if (o < w.cout_r && c < w.cin_r)
+            w.flat[((size_t)o * 9 + tap) * w.cin_r + c] = v;
+    } else {
+        const int o = (int)(q - w.nw);
+        if (o < w.cout_r)
+            w.flat[(size_t)w.cout_r * 9 * w.cin_r + o] = v;
+    }
+}
+
 __global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ part, int ns, int stride, size_t n,
-                                                    float *__restrict__ out)
+                                                    RowOut out)
 {
     const size_t n4 = n / 4;
     for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n4; q += (size_t)gridDim.x * kT) {
@@ -886,10 +920,10 @@ __global__ __launch_bounds__(kT) void k_reduce_rows(const float *__restrict__ pa
             a.z += v.z;
             a.w += v.w;
         }
-        out[4 * q] = a.x;
-        out[4 * q + 1] = a.y;
-        out[4 * q + 2] = a.z;
-        out[4 * q + 3] = a.w;
+        put_col(out, 4 * q, a.x);
+        put_col(out, 4 * q + 1, a.y);
+        put_col(out, 4 * q + 2, a.z);
+        put_col(out, 4 * q + 3, a.w);
     }
 }
 
@@ -1274,41 +1308,46 @@ __global__ __launch_bounds__(64) void k_clip_scale(const double *__restrict__ pa
     state[3] += 1.f;
 }
 
-// Layer weights from the flat master vector: wq [cout][9][cin] bf16 (zero
-// for padded channels), bias [cout] float.
-__global__ __launch_bounds__(kT) void k_requant(const float *__restrict__ master, __bf16 *__restrict__ wq,
-                                                float *__restrict__ bias, int cout, int cin, int cout_r, int cin_r)
-{
-    const size_t n = (size_t)cout * 9 * cin;
-    const float *wm = master;
-    const float *bm = master + (size_t)cout_r * 9 * cin_r;
-    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n + cout; q += (size_t)gridDim.x * kT) {
-        if (q < n) {
-            const int c = (int)(q % cin);
-            const int tap = (int)((q / cin) % 9);
-            const int o = (int)(q / ((size_t)9 * cin));
-            wq[q] = (__bf16)((o < cout_r && c < cin_r) ? wm[((size_t)o * 9 + tap) * cin_r + c] : 0.f);
-        } else {
-            const int o = (int)(q - n);
-            bias[o] = o < cout_r ? bm[o] : 0.f;
-        }
-    }
-}
+// One layer's parameter shapes for k_requant_all.
+struct LayerDev {
+    long long off;   // its slice of the flat parameters: weights [cout_r][9][cin_r], then bias [cout_r]
+    long long start; // its first element in the launch's index space (cout 9 cin + cout elements each)
+    __bf16 *wq;      // [cout][9][cin] (padding channels zero)
+    __bf16 *wd;      // [cin][9][cout], taps reversed: the input gradient's weights
+    float *bias;     // [cout]
+    int cout, cin, cout_r, cin_r;
+};
+constexpr int kMaxLayers = 16;
 
-// Flat gradient of one layer from the padded weight gradient dw [cout][9][cin]
-// and bias gradient db [cout].
-__global__ __launch_bounds__(kT) void k_grad_to_flat(const float *__restrict__ dw, const float *__restrict__ db,
-                                                     float *__restrict__ flat, int cout, int cin, int cout_r, int cin_r)
+// From the float32 master parameters, for every layer at once: the bf16
+// weights of the forward convolution, the same weights flipped and
+// transposed for the input gradient (Wd[c][8 - tap][o] = W[o][tap][c]) and
+// the float32 bias, each padded with zeros to the stored channel counts.
+__global__ __launch_bounds__(kT) void k_requant_all(const float *__restrict__ master,
+                                                    const LayerDev *__restrict__ tab, int nl, long long total)
 {
-    const size_t n = (size_t)cout_r * 9 * cin_r;
-    for (size_t q = (size_t)blockIdx.x * kT + threadIdx.x; q < n + cout_r; q += (size_t)gridDim.x * kT) {
-        if (q < n) {
-            const int c = (int)(q % cin_r);
-            const int tap = (int)((q / cin_r) % 9);
-            const int o = (int)(q / ((size_t)9 * cin_r));
-            flat[q] = dw[((size_t)o * 9 + tap) * cin + c];
+    __shared__ LayerDev t[kMaxLayers];
+    for (int i = threadIdx.x; i < nl; i += kT)
+        t[i] = tab[i];
+    __syncthreads();
+    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < total; q += (long long)gridDim.x * kT) {
+        int li = 0;
+        while (li + 1 < nl && t[li + 1].start <= q)
+            ++li;
+        const LayerDev &l = t[li];
+        const long long e = q - l.start;
+        const long long n = (long long)l.cout * 9 * l.cin;
+        const float *wm = master + l.off;
+        if (e < n) {
+            const int c = (int)(e % l.cin);
+            const int tap = (int)((e / l.cin) % 9);
+            const int o = (int)(e / (9LL * l.cin));
+            const __bf16 v = (__bf16)((o < l.cout_r && c < l.cin_r) ? wm[((size_t)o * 9 + tap) * l.cin_r + c] : 0.f);
+            l.wq[e] = v;
+            l.wd[((size_t)c * 9 + (8 - tap)) * l.cout + o] = v;
         } else {
-            flat[q] = db[q - n];
+            const int o = (int)(e - n);
+            l.bias[o] = o < l.cout_r ? wm[(size_t)l.cout_r * 9 * l.cin_r + o] : 0.f;
         }
     }
 }
@@ -1469,8 +1508,9 @@ int conv_dgrad(Work &wk, const __bf16 *dy, int B, int H, int W, int Cout, const 
     return conv_fwd(dy, B, H, W, Cout, wk.wd, nullptr, Cin, 0, mask, dx, false, st);
 }
 
-// out[q] = fixed-order sum of the ns rows of part [ns][n] (overwrites part).
-void reduce_rows(float *part, int ns, size_t n, float *out, hipStream_t st)
+// Column q of the fixed-order sum of the ns rows of part [ns][n] goes where
+// `out` says (overwrites part).
+void reduce_rows(float *part, int ns, size_t n, const RowOut &out, hipStream_t st)
 {
     const long long n4 = (long long)(n / 4);
     int stride = 1;
@@ -1501,15 +1541,18 @@ int wgrad_width(int C)
 }
 
 template <int OW, int WC>
-void wgrad_launch(dim3 grid, const __bf16 *x, const __bf16 *dy, float *part, float *bp, int H, int W, int Cin,
-                  int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, hipStream_t st)
+void wgrad_launch(dim3 grid, const __bf16 *x, const __bf16 *dy, float *part, size_t rs, int with_bias, int H, int W,
+                  int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_wgrad<OW, WC>), grid, dim3(64 * WC), 0, st, x, dy, part, bp, H, W, Cin, Cout, n_ct,
-                       tiles_x, tiles_y, tiles, tpr);
+    hipLaunchKernelGGL((k_wgrad<OW, WC>), grid, dim3(64 * WC), 0, st, x, dy, part, rs, with_bias, H, W, Cin, Cout,
+                       n_ct, tiles_x, tiles_y, tiles, tpr);
 }
 
-int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, float *dw,
-               float *db, hipStream_t st)
+// Weight gradient [Cout][9][Cin] and, with out.db or out.flat, the bias
+// gradient, summed over the pixel ranges in one fixed-order reduction and
+// written where `out` says (out.nw and out.cin are filled in here).
+int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, RowOut out,
+               hipStream_t st)
 {
     const int WC = wgrad_width(Cin);
     const int OW = wgrad_width(Cout) > WC ? (WC == 1 ? 1 : 3) : wgrad_width(Cout);
@@ -1519,11 +1562,15 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
     const long long tiles = (long long)B * tiles_x * tiles_y;
     const int K = 9 * Cin;
     const size_t n = (size_t)Cout * K;
+    const int with_bias = (out.db || out.flat) ? 1 : 0;
+    const size_t rs = n + (with_bias ? (size_t)Cout : 0);  // a multiple of 4 (Cin, Cout multiples of 8)
+    out.nw = n;
+    out.cin = Cin;
     const long long per_range = (long long)n_ot * n_ct;
     // pixel ranges: ~1024 workgroups in all, as long as the partial sums stay
     // within 64 MB, but at least enough to give every CU one workgroup
     long long ns = 1024 / per_range;
-    const long long cap = (64LL << 20) / (long long)((n + Cout) * sizeof(float));
+    const long long cap = (64LL << 20) / (long long)(rs * sizeof(float));
     ns = ns > cap ? cap : ns;
     const long long floor_ns = (256 + per_range - 1) / per_range;
     ns = ns < floor_ns ? floor_ns : ns;
@@ -1531,19 +1578,17 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
     ns = ns < 1 ? 1 : ns;
     const long long tpr = (tiles + ns - 1) / ns;
     ns = (tiles + tpr - 1) / tpr;
-    const size_t need = ((size_t)ns * n + (size_t)ns * Cout) * sizeof(float);
+    const size_t need = (size_t)ns * rs * sizeof(float);
     TVSPEC_TRY(ensure((void **)&wk.part, &wk.part_bytes, need));
-    float *bp = db ? wk.part + (size_t)ns * n : nullptr;
     const dim3 grid((unsigned)per_range, (unsigned)ns);
     const int ti = (int)tiles, tp = (int)tpr;
 #define TVSPEC_WG(ow, wc)                                                                                       \
     if (OW == ow && WC == wc)                                                                                   \
-        wgrad_launch<ow, wc>(grid, x, dy, wk.part, bp, H, W, Cin, Cout, n_ct, tiles_x, tiles_y, ti, tp, st);
+        wgrad_launch<ow, wc>(grid, x, dy, wk.part, rs, with_bias, H, W, Cin, Cout, n_ct, tiles_x, tiles_y, ti, tp, \
+                             st);
     TVSPEC_WG(1, 1) TVSPEC_WG(1, 3) TVSPEC_WG(1, 4) TVSPEC_WG(3, 3) TVSPEC_WG(3, 4) TVSPEC_WG(4, 4)
 #undef TVSPEC_WG
-    reduce_rows(wk.part, (int)ns, n, dw, st);
-    if (db)
-        reduce_rows(bp, (int)ns, (size_t)Cout, db, st);
+    reduce_rows(wk.part, (int)ns, rs, out, st);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1568,9 +1613,8 @@ struct Layer {
     int cin, cout;       // as stored (input padded to 8, output to 16)
     long long off;       // offset of the weights in the flat parameter vector
     __bf16 *wq = nullptr;
+    __bf16 *wd = nullptr;  // flipped, transposed copy for the input gradient
     float *bias = nullptr;
-    float *dw = nullptr; // padded weight gradient
-    float *db = nullptr;
 };
 
 struct Act {
@@ -1604,6 +1648,8 @@ struct tvspec_net {
     float *oscale = nullptr;  // [16] output channel scales (1 by default)
     int lblk = 0;
     int otiles = 0;           // 8 x 32 output tiles per image (identity partials of the forward pass)
+    tvspec::nn::LayerDev *ltab = nullptr;  // the layers' shapes for k_requant_all
+    long long lcount = 0;                  // elements k_requant_all covers
     tvspec::nn::Work wk;
     std::vector<void *> allocs;
     std::mutex mu;
@@ -1642,11 +1688,8 @@ double normal(uint64_t &s)
 
 int requant_all(tvspec_net *n, hipStream_t st)
 {
-    for (Layer &l : n->L) {
-        const size_t cnt = (size_t)l.cout * 9 * l.cin + l.cout;
-        hipLaunchKernelGGL(k_requant, dim3(grid_for((long long)cnt)), dim3(kT), 0, st, n->master + l.off, l.wq,
-                           l.bias, l.cout, l.cin, l.cout_r, l.cin_r);
-    }
+    hipLaunchKernelGGL(k_requant_all, dim3(grid_for(n->lcount)), dim3(kT), 0, st, n->master, n->ltab,
+                       (int)n->L.size(), n->lcount);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1738,10 +1781,15 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     // of its input masked by mask_in (the input's own ReLU) or unmasked
     auto layer = [&](int li, int in, const __bf16 *dz, int din, bool mask_in) -> int {
         const Layer &l = n->L[li];
-        TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, l.dw, l.db, st));
+        RowOut go;  // straight into the layer's slice of the flat gradient
+        go.flat = n->grad + l.off;
+        go.cout_r = l.cout_r;
+        go.cin_r = l.cin_r;
+        TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st));
+        // input gradient: the forward kernel on the layer's flipped weights
         if (din >= 0)
-            TVSPEC_TRY(conv_dgrad(wk, dz, B, A[in].H, A[in].W, l.cout, l.wq, l.cin, mask_in ? A[in].a : nullptr,
-                                  A[din].g, st));
+            TVSPEC_TRY(conv_fwd(dz, B, A[in].H, A[in].W, l.cout, l.wd, nullptr, l.cin, 0,
+                                mask_in ? A[in].a : nullptr, A[din].g, false, st));
         return TVSPEC_OK;
     };
     auto upcat_bwd = [&](int cat, int low, int skip) {
@@ -1776,11 +1824,6 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     pool_bwd(E1B, P1);
     TVSPEC_TRY(layer(1, E1A, A[E1B].g, E1A, true));
     TVSPEC_TRY(layer(0, X0, A[E1A].g, -1, false));
-    for (Layer &l : n->L) {
-        const size_t cnt = (size_t)l.cout_r * 9 * l.cin_r + l.cout_r;
-        hipLaunchKernelGGL(k_grad_to_flat, dim3(grid_for((long long)cnt)), dim3(kT), 0, st, l.dw, l.db,
-                           n->grad + l.off, l.cout, l.cin, l.cout_r, l.cin_r);
-    }
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
@@ -1842,8 +1885,10 @@ extern "C" int tvspec_nn_conv3x3_wgrad(const void *x, const void *dy, int B, int
     std::lock_guard<std::mutex> lock(g_raw_mu);
     Work *wk = nullptr;
     TVSPEC_TRY(raw_work(&wk));
-    return conv_wgrad(*wk, (const __bf16 *)x, (const __bf16 *)dy, B, H, W, Cin, Cout, dw, db,
-                      (hipStream_t)stream);
+    RowOut out;
+    out.dw = dw;
+    out.db = db;
+    return conv_wgrad(*wk, (const __bf16 *)x, (const __bf16 *)dy, B, H, W, Cin, Cout, out, (hipStream_t)stream);
 }
 
 extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long seed, tvspec_net **out)
@@ -1888,14 +1933,28 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
         if (rc == TVSPEC_OK)
             rc = net_alloc(n, (void **)&l.bias, (size_t)l.cout * sizeof(float));
         if (rc == TVSPEC_OK)
-            rc = net_alloc(n, (void **)&l.dw, (size_t)l.cout * 9 * l.cin * sizeof(float));
-        if (rc == TVSPEC_OK)
-            rc = net_alloc(n, (void **)&l.db, (size_t)l.cout * sizeof(float));
+            rc = net_alloc(n, (void **)&l.wd, (size_t)l.cout * 9 * l.cin * sizeof(__bf16));
         if (rc != TVSPEC_OK)
             return cleanup(rc);
         n->L.push_back(l);
     }
     n->nparams = off;
+    {
+        LayerDev tab[kMaxLayers];
+        long long start = 0;
+        for (size_t i = 0; i < n->L.size(); ++i) {
+            const Layer &l = n->L[i];
+            tab[i] = LayerDev{l.off, start, l.wq, l.wd, l.bias, l.cout, l.cin, l.cout_r, l.cin_r};
+            start += (long long)l.cout * 9 * l.cin + l.cout;
+        }
+        n->lcount = start;
+        int rc = net_alloc(n, (void **)&n->ltab, n->L.size() * sizeof(LayerDev));
+        if (rc == TVSPEC_OK && hipMemcpy(n->ltab, tab, n->L.size() * sizeof(LayerDev), hipMemcpyHostToDevice) !=
+                                   hipSuccess)
+            rc = fail(TVSPEC_EDEVICE, "hipMemcpy failed");
+        if (rc != TVSPEC_OK)
+            return cleanup(rc);
+    }
     const size_t pb = (size_t)off * sizeof(float);
     for (float **p : {&n->master, &n->grad, &n->m, &n->v}) {
         const int rc = net_alloc(n, (void **)p, pb);
@@ -2115,7 +2174,7 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
                                      int B, float lr, float *loss, void *stream)
 {
     g_last_error.clear();
-    if (!net || !f || !bands || !residual || !loss)
+    if (!net || !f || !bands || !residual)
         return fail(TVSPEC_EINVAL, "null pointer argument");
     if (!(lr > 0.f) || !std::isfinite(lr))
         return fail(TVSPEC_EINVAL, "lr must be finite and > 0");
@@ -2134,6 +2193,20 @@ extern "C" int tvspec_net_train_step(tvspec_net *net, const float *f, const doub
     hipLaunchKernelGGL(k_adam, dim3(grid_for(net->nparams)), dim3(kT), 0, st, net->master, net->grad, net->m, net->v,
                        net->nparams, lr, b1, b2, 1e-8f, c1, c2, net->gstate + 2);
     TVSPEC_TRY(requant_all(net, st));
+    if (!loss)
+        return TVSPEC_OK;
+    HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return TVSPEC_OK;
+}
+
+extern "C" int tvspec_net_last_loss(tvspec_net *net, float *loss, void *stream)
+{
+    g_last_error.clear();
+    if (!net || !loss)
+        return fail(TVSPEC_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lock(net->mu);
+    hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return TVSPEC_OK;

@@ -29,6 +29,7 @@ EXPORTS = (
     "tvspec_net_forward",
     "tvspec_net_forward_checked",
     "tvspec_net_train_step",
+    "tvspec_net_last_loss",
     "tvspec_net_loss_grad",
     "tvspec_net_identity_error",
     "tvspec_net_destroy",
@@ -70,6 +71,8 @@ _lib.tvspec_net_forward.restype = _i
 _lib.tvspec_net_forward_checked.argtypes = [_vp, _vp, _i, _vp, _vp, _vp]
 _lib.tvspec_net_forward_checked.restype = _i
 _lib.tvspec_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i, _f, ctypes.POINTER(_f), _vp]
+_lib.tvspec_net_last_loss.argtypes = [_vp, ctypes.POINTER(_f), _vp]
+_lib.tvspec_net_last_loss.restype = _i
 _lib.tvspec_net_train_step.restype = _i
 _lib.tvspec_net_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_f), _vp, _vp]
 _lib.tvspec_net_loss_grad.restype = _i
@@ -185,10 +188,19 @@ def tvspec_net_forward_checked(h, f, out, err, stream=None):
                                            err.data_ptr() if err is not None else None, _stream(f, stream)))
 
 
-def tvspec_net_train_step(h, f, bands, residual, lr, stream=None):
+def tvspec_net_train_step(h, f, bands, residual, lr, stream=None, sync=True):
+    """One step; returns the loss (sync=True) or None (the step is only
+    enqueued; tvspec_net_last_loss reads the latest loss later)."""
     loss = _f(0.0)
     _check(_lib.tvspec_net_train_step(h, f.data_ptr(), bands.data_ptr(), residual.data_ptr(), f.shape[0],
-                                      float(lr), ctypes.byref(loss), _stream(f, stream)))
+                                      float(lr), ctypes.byref(loss) if sync else None, _stream(f, stream)))
+    return loss.value if sync else None
+
+
+def tvspec_net_last_loss(h, stream=None, device=None):
+    loss = _f(0.0)
+    st = stream.cuda_stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+    _check(_lib.tvspec_net_last_loss(h, ctypes.byref(loss), st))
     return loss.value
 
 
@@ -285,10 +297,13 @@ class Net:
         tvspec_net_forward_checked(self._h, f, out, err, stream)
         return out, err
 
-    def train_step(self, f, bands, residual, lr, stream=None):
+    def train_step(self, f, bands, residual, lr, stream=None, sync=True):
         self._check_f(f)
         self._check_target(f, bands, residual)
-        return tvspec_net_train_step(self._h, f, bands, residual, lr, stream)
+        return tvspec_net_train_step(self._h, f, bands, residual, lr, stream, sync)
+
+    def last_loss(self, stream=None):
+        return tvspec_net_last_loss(self._h, stream)
 
     def loss_grad(self, f, bands, residual, grads=True, stream=None):
         self._check_f(f)

@@ -128,17 +128,23 @@ def output_scales(bands, res):
     return s
 
 
-def train(net, f, bands, res, steps, batch, lr, seed=0):
+def train(net, f, bands, res, steps, batch, lr, seed=0, loss_every=1):
     """`steps` Adam steps on minibatches drawn uniformly from the dataset;
-    lr is a number or a function of the step index (0 .. steps - 1)."""
+    lr is a number or a function of the step index (0 .. steps - 1).
+    Returns the losses of every loss_every-th step and of the last one; the
+    steps in between are only enqueued, so the device runs ahead while the
+    next minibatch is drawn."""
     g = torch.Generator().manual_seed(seed)
     n = f.shape[0]
     losses = []
     for i in range(steps):
         idx = torch.randint(0, n, (batch,), generator=g).to(f.device)
         rate = lr(i) if callable(lr) else lr
-        losses.append(net.train_step(f.index_select(0, idx).contiguous(), bands.index_select(0, idx).contiguous(),
-                                     res.index_select(0, idx).contiguous(), float(rate)))
+        sync = (i + 1) % loss_every == 0 or i == steps - 1
+        loss = net.train_step(f.index_select(0, idx).contiguous(), bands.index_select(0, idx).contiguous(),
+                              res.index_select(0, idx).contiguous(), float(rate), sync=sync)
+        if sync:
+            losses.append(loss)
     return losses
 
 

@@ -368,6 +368,26 @@ def test_training_is_deterministic(nn):
     assert np.array_equal(params[0], params[1])
 
 
+def test_enqueued_training_steps_equal_synchronised_ones(nn):
+    """Steps only enqueued (no loss read back) do the same work: the same
+    parameters and, read afterwards with tvspec_net_last_loss, the same last
+    loss as steps that each wait for their loss."""
+    f, bands, res = inputs(12, B=2, H=64, W=64)
+    ft, bt, rt = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (f, bands, res))
+    params, last = [], []
+    for sync in (True, False):
+        net = nn.Net(64, 64, 2, seed=22)
+        net.set_output_scale(np.linspace(0.05, 0.5, 15).astype(np.float32))
+        net.set_grad_clip(2.0)
+        out = [net.train_step(ft, bt, rt, 1e-3, sync=sync) for _ in range(6)]
+        assert (out[-1] is not None) == sync
+        last.append(net.last_loss())
+        params.append(net.get_params())
+        net.close()
+    assert last[0] == last[1]
+    assert np.array_equal(params[0], params[1])
+
+
 def test_gradient_clipping(nn):
     """The first step's gradient norm is the norm of the gradient loss_grad
     returns and seeds the running average (no scaling); a batch whose
