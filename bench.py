@@ -118,6 +118,17 @@ def alu_roofline(kernel, t, ms_per_step, precision, flops_per_pit, bytes_per_pit
     return rec
 
 
+def whole_job_alu(pixel_iters, seconds, precision="mixed"):
+    """The whole-job counterpart of the kernel roofline: 18 flops per
+    pixel-iteration (one Chambolle update) over the job's wall time, against
+    the vector-ALU peak of the mode.  It includes every idle gap, queueing
+    and the per-solve kernels, so it bounds the tile kernel's own fraction
+    from below."""
+    tf = FLOPS_PER_PIXEL_ITER * pixel_iters / seconds / 1e12
+    return {"pixel_iters": pixel_iters, "achieved_TFLOPs": tf, "peak_TFLOPs": ALU_PEAK_TFLOPS[precision],
+            "frac": tf / ALU_PEAK_TFLOPS[precision], "kind": "whole job (wall time)"}
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -155,7 +166,7 @@ def cpu_model():
     return " ".join(parts)
 
 
-def cpu_baseline(f, wl, one_thread_steps=12):
+def cpu_baseline(f, wl, one_thread_steps=12, others=True):
     """Time the FP64 CPU oracle on the full workload (all host threads), and
     on one thread over the first `one_thread_steps` flow steps of the same
     workload (a child process with OMP_NUM_THREADS=1), scaled per ROF solve
@@ -191,7 +202,37 @@ def cpu_baseline(f, wl, one_thread_steps=12):
                              "sample": "the first %d flow steps (%d ROF solves x %d iterations), %.1f s, scaled per "
                                        "solve to the %d solves of the workload" % (k1, k1 + 1, wl["inner_iters"], s1,
                                                                                    wl["K"] + 1)}
+    if others:
+        rec["other_workloads"] = oracle_other_workloads()
     return rec
+
+
+def oracle_other_workloads(mega_steps=2):
+    """The oracle (all host threads) on the two other plain-path workloads:
+    the 64x64 parity workload in full, and the 3x1024x1024 megapixel flow
+    (dt 0.002, K 300, 200 iterations) over its first `mega_steps` flow
+    steps, scaled per ROF solve to the 301 solves of the full call."""
+    import oracle
+    from paper_2006_10004_amd import synth
+    out = {}
+    f64 = synth.shapes_image(synth.SMALL_64, 0)
+    t0 = time.perf_counter()
+    oracle.decompose(f64, 0.005, 60, 200, [0, 1, 2, 4, 60], tau=WORKLOAD["tau"])
+    s = time.perf_counter() - t0
+    out["64x64"] = {"value": 64 * 64 / 1e6 / s, "unit": "MPix/s", "cores": oracle.num_threads(), "seconds": s,
+                    "sample": "one full decomposition of the 64x64 workload (dt 0.005, K 60, 61 ROF solves x 200 "
+                              "iterations)"}
+    fm = synth.shapes_image(synth.megapixel_spec(1024), 61000)
+    t0 = time.perf_counter()
+    oracle.decompose(fm, 0.002, mega_steps, 200, [0, mega_steps], tau=WORKLOAD["tau"])
+    s = time.perf_counter() - t0
+    full = s * 301 / (mega_steps + 1)
+    out["3x1024x1024"] = {"value": 1024 * 1024 / 1e6 / full, "unit": "MPix/s", "cores": oracle.num_threads(),
+                          "seconds_full_estimate": full,
+                          "sample": "the first %d flow steps of the megapixel flow (dt 0.002, %d ROF solves x 200 "
+                                    "iterations on 3 x 1024 x 1024), %.1f s, scaled per solve to the 301 solves of "
+                                    "K = 300" % (mega_steps, mega_steps + 1, s)}
+    return out
 
 
 def pdhg_block(f, wl, edges, precision, steps):
@@ -508,8 +549,10 @@ def megapixel_serving(net, sides, n_req, seed):
         print("bench: megapixel plain path, its own flow, %dx%d: %.0f ms" % (side, side, tm * 1e3), file=sys.stderr,
               flush=True)
     rec["paper_context"] = dict(PAPER_1024_CONTEXT)
+    pit = sum(3 * side * side * (flow["K"] + 1) * flow["iters"] for side in sides)
     rec["plain_megapixel_flow"] = {"flow": flow, "sides": list(sides), "ms": lat_m,
                                    "MPix_per_s": mp_m / (sum(lat_m) / 1e3),
+                                   "alu_roofline": whole_job_alu(pit, sum(lat_m) / 1e3),
                                    "surrogate_speedup": rec["surrogate"]["MPix_per_s"] / (mp_m / (sum(lat_m) / 1e3))}
     for v in svc.values():
         v.net.close()
@@ -594,7 +637,9 @@ def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
             if ls:
                 per_side[str(side)] = {"n": len(ls), "p50_ms": percentile(ls, 50), "p99_ms": percentile(ls, 99)}
         worst = max(float(out["stats"][0]) for _, _, out in jobs)
+        pit = sum(C * s * s * (K + 1) * sv["inner_iters"] for s, _, _ in jobs)
         return {"requests": len(jobs), "makespan_s": end, "MPix_per_s": px / 1e6 / end,
+                "alu_roofline": whole_job_alu(pit, end, precision),
                 "channel_MPix_per_s": C * px / 1e6 / end, "req_per_s": len(jobs) / end,
                 "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                 "mean_ms": float(np.mean(lat)), "queue_p99_ms": percentile([done[i]["queue_ms"] for i in done], 99),

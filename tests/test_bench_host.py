@@ -66,10 +66,31 @@ def test_cpu_baseline_reports_all_threads_and_one_thread():
     from paper_2006_10004_amd import synth
     f = synth.shapes_image(synth.ShapeSpec(32, 40, 1), 3)
     wl = dict(H=32, W=40, C=1, dt=0.01, K=6, inner_iters=20, n_bands=3, tau=0.248)
-    rec = bench.cpu_baseline(f, wl, one_thread_steps=2)
+    rec = bench.cpu_baseline(f, wl, one_thread_steps=2, others=False)
     assert rec["kind"] == "oracle" and rec["unit"] == "MPix/s"
     assert rec["value"] > 0 and rec["cores"] >= 1
     assert "7 ROF solves x 20 iterations" in rec["sample"]
     one = rec["one_thread"]
     assert one["cores"] == 1 and one["value"] > 0
     assert "3 ROF solves" in one["sample"]
+
+
+def test_oracle_on_the_other_workloads():
+    """The 64x64 workload in full and the megapixel flow per solve, scaled
+    to its 301 solves."""
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = bench.oracle_other_workloads(mega_steps=1)
+    small, mega = rec["64x64"], rec["3x1024x1024"]
+    assert small["unit"] == "MPix/s" and abs(small["value"] - 64 * 64 / 1e6 / small["seconds"]) < 1e-12
+    assert "61 ROF solves x 200" in small["sample"]
+    assert abs(mega["value"] - 1024 * 1024 / 1e6 / mega["seconds_full_estimate"]) < 1e-12
+    assert "2 ROF solves x 200" in mega["sample"] and "301 solves" in mega["sample"]
+
+
+def test_whole_job_alu_fraction():
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.whole_job_alu(2_000_000_000, 0.5, "mixed")
+    assert abs(r["achieved_TFLOPs"] - 18 * 4e9 / 1e12) < 1e-12
+    assert r["peak_TFLOPs"] == 78.6 and abs(r["frac"] - r["achieved_TFLOPs"] / 78.6) < 1e-15
