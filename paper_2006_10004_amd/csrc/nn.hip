@@ -1108,16 +1108,21 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh)
     return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// err[b] = (sum of part[b][0..nblk) in order) / (3 HW).
-__global__ __launch_bounds__(kT) void k_identity_total(const double *__restrict__ part, int B, int nblk, long long HW,
+// err[b] = (sum of part[b][0..nblk)) / (3 HW), one block per image: thread
+// t adds entries t, t + 256, ... in order, then the block's fixed-order
+// tree (so the value is deterministic; a megapixel image has 16384 tile
+// partials, which one thread alone adds too slowly).  Grid (B).
+__global__ __launch_bounds__(kT) void k_identity_total(const double *__restrict__ part, int nblk, long long HW,
                                                        float *__restrict__ err)
 {
-    for (int b = threadIdx.x; b < B; b += kT) {
-        double s = 0.0;
-        for (int k = 0; k < nblk; ++k)
-            s += part[(size_t)b * nblk + k];
+    __shared__ double sh[kT / 64];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kT)
+        s += part[(size_t)b * nblk + k];
+    s = block_sum_d(s, sh);
+    if (threadIdx.x == 0)
         err[b] = (float)(s / (3.0 * (double)HW));
-    }
 }
 
 __device__ __forceinline__ float block_sum(float v, float *sh)
@@ -2141,7 +2146,7 @@ extern "C" int tvspec_net_forward_checked(tvspec_net *net, const float *f, int B
     TVSPEC_TRY(forward(net, f, B, st, false, out, err ? net->ipart : nullptr));
     const long long HW = (long long)net->H * net->W;
     if (err)
-        hipLaunchKernelGGL(k_identity_total, dim3(1), dim3(kT), 0, st, net->ipart, B, net->otiles, HW, err);
+        hipLaunchKernelGGL(k_identity_total, dim3(B), dim3(kT), 0, st, net->ipart, net->otiles, HW, err);
     HIP_TRY(hipGetLastError());
     return TVSPEC_OK;
 }
