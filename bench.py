@@ -559,7 +559,7 @@ def megapixel_serving(net, sides, n_req, seed):
     return rec
 
 
-def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
+def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4, fixed_requests=SERVING_FIXED_REQUESTS):
     """The serving workload through the server: first a burst of `burst`
     requests submitted at once (sustainable throughput), then n_req requests
     with Poisson arrivals at `rate` per second (0: 85% of the burst's
@@ -670,12 +670,13 @@ def serving_bench(n_req, rate, burst, budget_gb, precision, seed=7, pool=4):
         del jobs
         print("bench: serving Poisson run done (p99 %.0f ms)" % rec["poisson"]["p99_ms"], file=sys.stderr,
               flush=True)
-        jobs = make_jobs(SERVING_FIXED_REQUESTS)
-        arrivals = np.cumsum(rng.exponential(1.0 / SERVING_FIXED_RATE, size=SERVING_FIXED_REQUESTS))
-        arrivals -= arrivals[0]
-        rec["poisson_fixed_rate"] = run(srv, jobs, list(arrivals))
-        rec["poisson_fixed_rate"]["rate_req_per_s"] = SERVING_FIXED_RATE
-        del jobs
+        if fixed_requests > 0:
+            jobs = make_jobs(fixed_requests)
+            arrivals = np.cumsum(rng.exponential(1.0 / SERVING_FIXED_RATE, size=fixed_requests))
+            arrivals -= arrivals[0]
+            rec["poisson_fixed_rate"] = run(srv, jobs, list(arrivals))
+            rec["poisson_fixed_rate"]["rate_req_per_s"] = SERVING_FIXED_RATE
+            del jobs
         info = srv.info()
     rec["server"] = {k: info[k] for k in ("max_in_flight", "graph_builds", "buckets", "steps", "replays", "peak_bytes")}
     return rec
@@ -698,6 +699,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate, requests/s (0 = 85%% of the burst's rate)")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-fixed-requests", type=int, default=SERVING_FIXED_REQUESTS,
+                    help="requests of the Poisson run at a fixed %g requests/s (0 = skip)" % SERVING_FIXED_RATE)
     ap.add_argument("--pdhg-steps", type=int, default=3,
                     help="also time this many decompositions with the primal-dual solver (0 = skip)")
     ap.add_argument("--sur-train-images", type=int, default=8192,
@@ -836,7 +839,8 @@ def main():
 
     if args.serve_requests > 0:
         rec["serving"] = serving_bench(args.serve_requests, args.serve_rate, args.serve_burst,
-                                       args.serve_budget_gb, args.precision)
+                                       args.serve_budget_gb, args.precision,
+                                       fixed_requests=args.serve_fixed_requests)
         print("bench: serving pass done", file=sys.stderr, flush=True)
 
     if args.sur_train_images > 0:

@@ -28,8 +28,9 @@
 //                  transposing LDS read (ds_read_b64_tr_b16); per-range
 //                  partial sums are added in a fixed order by k_reduce_rows
 //                  (deterministic).
-//   the rest       packing, 2x2 max-pooling, nearest upsampling with skip
-//                  concatenation, their gradients (ReLU masks fused), the
+//   the rest       packing, 2x2 max-pooling and its gradient, the gradient
+//                  of the decoder's concatenations (which the convolutions and
+//                  weight gradients read in place; ReLU masks fused), the
 //                  normalised MSE loss and its gradient, Adam.
 
 #include <hip/hip_runtime.h>
@@ -668,7 +669,7 @@ template <int OW, int WC>
 __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
                                                    float *__restrict__ part, size_t rs, int with_bias, int H, int W,
                                                    int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles,
-                                                   int tpr)
+                                                   int tpr, const __bf16 *__restrict__ Xlow, int Clow)
 {
     constexpr int kNT = 64 * WC;
     constexpr int kOT = 16 * OW;               // output channels of the workgroup
@@ -751,8 +752,12 @@ __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__
                 const int yy = y0 + hr - 1;
                 const int xx = x0 + pix - hr * kGHX - 1;
                 const int c = c0 + 8 * grp;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W && c < Cin)
-                    src = X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + c;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W && c < Cin) {
+                    if (c < Clow)  // the upsampled half of a concatenated input, read in place
+                        src = Xlow + ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow + c;
+                    else
+                        src = X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) + (c - Clow);
+                }
             }
             vx[j] = *(const global_bf16x8 *)src;
         }
@@ -1016,29 +1021,9 @@ __global__ __launch_bounds__(kT) void k_maxpool_bwd(const __bf16 *__restrict__ x
     }
 }
 
-// out [B][2h][2w][C1 + C2] = [nearest-upsampled low [B][h][w][C1], skip].
-__global__ __launch_bounds__(kT) void k_up_concat(const __bf16 *__restrict__ low, const __bf16 *__restrict__ skip,
-                                                  __bf16 *__restrict__ out, int B, int H, int W, int C1, int C2)
-{
-    const int C = C1 + C2, cg = C / 8;
-    const long long n = (long long)B * H * W * cg;
-    for (long long q = (long long)blockIdx.x * kT + threadIdx.x; q < n; q += (long long)gridDim.x * kT) {
-        const int c8 = (int)(q % cg) * 8;
-        const long long p = q / cg;
-        const int x = (int)(p % W);
-        const int y = (int)((p / W) % H);
-        const long long b = p / ((long long)W * H);
-        bf16x8 v;
-        if (c8 < C1)
-            v = *(const bf16x8 *)(low + ((size_t)(b * (H / 2) + y / 2) * (W / 2) + x / 2) * C1 + c8);
-        else
-            v = *(const bf16x8 *)(skip + (size_t)p * C2 + (c8 - C1));
-        *(bf16x8 *)(out + (size_t)p * C + c8) = v;
-    }
-}
-
-// Gradient of k_up_concat: dlow = (sum of the 4 children's first C1
-// channels) * (low > 0), dskip = (last C2 channels) * (skip > 0).
+// Gradient of the concatenation [nearest-upsampled low, skip] in its two
+// sources: dlow = (sum of the 4 children's first C1 channels) * (low > 0),
+// dskip = (last C2 channels) * (skip > 0).
 __global__ __launch_bounds__(kT) void k_up_concat_bwd(const __bf16 *__restrict__ dcat, const __bf16 *__restrict__ low,
                                                       const __bf16 *__restrict__ skip, __bf16 *__restrict__ dlow,
                                                       __bf16 *__restrict__ dskip, int B, int H, int W, int C1, int C2)
@@ -1547,18 +1532,26 @@ int wgrad_width(int C)
 
 template <int OW, int WC>
 void wgrad_launch(dim3 grid, const __bf16 *x, const __bf16 *dy, float *part, size_t rs, int with_bias, int H, int W,
-                  int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, hipStream_t st)
+                  int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, const __bf16 *xlow,
+                  int clow, hipStream_t st)
 {
     hipLaunchKernelGGL((k_wgrad<OW, WC>), grid, dim3(64 * WC), 0, st, x, dy, part, rs, with_bias, H, W, Cin, Cout,
-                       n_ct, tiles_x, tiles_y, tiles, tpr);
+                       n_ct, tiles_x, tiles_y, tiles, tpr, xlow, clow);
 }
 
 // Weight gradient [Cout][9][Cin] and, with out.db or out.flat, the bias
 // gradient, summed over the pixel ranges in one fixed-order reduction and
-// written where `out` says (out.nw and out.cin are filled in here).
+// written where `out` says (out.nw and out.cin are filled in here).  With
+// xlow the input is the concatenation [nearest 2x upsampling of xlow
+// ([B][H/2][W/2][clow]), x ([B][H][W][Cin - clow])], read in place (H, W
+// even, clow a multiple of 8).
 int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W, int Cin, int Cout, RowOut out,
-               hipStream_t st)
+               hipStream_t st, const __bf16 *xlow = nullptr, int clow = 0)
 {
+    if (xlow && (clow <= 0 || clow >= Cin || clow % 8 || H % 2 || W % 2))
+        return fail(TVSPEC_EINVAL, "weight gradient of a concatenated input: bad shapes");
+    if (!xlow)
+        clow = 0;
     const int WC = wgrad_width(Cin);
     const int OW = wgrad_width(Cout) > WC ? (WC == 1 ? 1 : 3) : wgrad_width(Cout);
     const int n_ot = (Cout + 16 * OW - 1) / (16 * OW);
@@ -1590,7 +1583,7 @@ int conv_wgrad(Work &wk, const __bf16 *x, const __bf16 *dy, int B, int H, int W,
 #define TVSPEC_WG(ow, wc)                                                                                       \
     if (OW == ow && WC == wc)                                                                                   \
         wgrad_launch<ow, wc>(grid, x, dy, wk.part, rs, with_bias, H, W, Cin, Cout, n_ct, tiles_x, tiles_y, ti, tp, \
-                             st);
+                             xlow, clow, st);
     TVSPEC_WG(1, 1) TVSPEC_WG(1, 3) TVSPEC_WG(1, 4) TVSPEC_WG(3, 3) TVSPEC_WG(3, 4) TVSPEC_WG(4, 4)
 #undef TVSPEC_WG
     reduce_rows(wk.part, (int)ns, rs, out, st);
@@ -1699,10 +1692,10 @@ int requant_all(tvspec_net *n, hipStream_t st)
     return TVSPEC_OK;
 }
 
-// training: materialise the decoder's concatenations (the weight gradients
-// read them) and leave the output in n->out ([P][16]); otherwise the first
-// decoder convolution of each level reads the upsampled lower level and the
-// skip tensor in place, and the last layer writes the planar output
+// The first decoder convolution of each level reads the upsampled lower
+// level and the skip tensor in place (so does its weight gradient: no
+// concatenated tensor is ever written).  training: leave the output in
+// n->out ([P][16]); otherwise the last layer writes the planar output
 // `planar` (with the identity partials into ipart[b][tile] unless ipart is
 // null).
 int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training, float *planar = nullptr,
@@ -1721,11 +1714,6 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training,
         return conv_fwd(A[in].a, B, A[in].H, A[in].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false, st,
                         nullptr, nullptr, 0, A[pooled].a);
     };
-    auto upcat = [&](int low, int skip, int out) {
-        const long long cnt = (long long)B * A[out].H * A[out].W * (A[out].C / 8);
-        hipLaunchKernelGGL(k_up_concat, dim3(grid_for(cnt)), dim3(kT), 0, st, A[low].a, A[skip].a, A[out].a, B,
-                           A[out].H, A[out].W, A[low].C, A[skip].C);
-    };
     TVSPEC_TRY(conv(0, X0, E1A));
     TVSPEC_TRY(conv_pool(1, E1A, E1B, P1));
     TVSPEC_TRY(conv(2, P1, E2A));
@@ -1735,11 +1723,7 @@ int forward(tvspec_net *n, const float *f, int B, hipStream_t st, bool training,
     TVSPEC_TRY(conv(6, P3, E4A));
     TVSPEC_TRY(conv(7, E4A, E4B));
     // decoder level: concatenation [upsampled low, skip] -> conv li -> out
-    auto up_conv = [&](int low, int skip, int cat, int li, int out) -> int {
-        if (training) {
-            upcat(low, skip, cat);
-            return conv(li, cat, out);
-        }
+    auto up_conv = [&](int low, int skip, int /*cat*/, int li, int out) -> int {
         const Layer &l = n->L[li];
         return conv_fwd(A[skip].a, B, A[skip].H, A[skip].W, l.cin, l.wq, l.bias, l.cout, 1, nullptr, A[out].a, false,
                         st, nullptr, A[low].a, A[low].C);
@@ -1784,13 +1768,20 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     // layer li: input activation `in`, gradient of its (masked) output dz;
     // writes the layer's parameter gradients and, if din >= 0, the gradient
     // of its input masked by mask_in (the input's own ReLU) or unmasked
-    auto layer = [&](int li, int in, const __bf16 *dz, int din, bool mask_in) -> int {
+    // (a decoder level's first layer: `in` is the concatenation, whose
+    // weight gradient reads the lower level `low` and the skip tensor `skip`
+    // in place)
+    auto layer = [&](int li, int in, const __bf16 *dz, int din, bool mask_in, int low = -1, int skip = -1) -> int {
         const Layer &l = n->L[li];
         RowOut go;  // straight into the layer's slice of the flat gradient
         go.flat = n->grad + l.off;
         go.cout_r = l.cout_r;
         go.cin_r = l.cin_r;
-        TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st));
+        if (low >= 0)
+            TVSPEC_TRY(conv_wgrad(wk, A[skip].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st, A[low].a,
+                                  A[low].C));
+        else
+            TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st));
         // input gradient: the forward kernel on the layer's flipped weights
         if (din >= 0)
             TVSPEC_TRY(conv_fwd(dz, B, A[in].H, A[in].W, l.cout, l.wd, nullptr, l.cin, 0,
@@ -1810,13 +1801,13 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     };
     TVSPEC_TRY(layer(14, D1B, n->dout, D1B, true));
     TVSPEC_TRY(layer(13, D1A, A[D1B].g, D1A, true));
-    TVSPEC_TRY(layer(12, C1, A[D1A].g, C1, false));
+    TVSPEC_TRY(layer(12, C1, A[D1A].g, C1, false, D2B, E1B));
     upcat_bwd(C1, D2B, E1B);
     TVSPEC_TRY(layer(11, D2A, A[D2B].g, D2A, true));
-    TVSPEC_TRY(layer(10, C2, A[D2A].g, C2, false));
+    TVSPEC_TRY(layer(10, C2, A[D2A].g, C2, false, D3B, E2B));
     upcat_bwd(C2, D3B, E2B);
     TVSPEC_TRY(layer(9, D3A, A[D3B].g, D3A, true));
-    TVSPEC_TRY(layer(8, C3, A[D3A].g, C3, false));
+    TVSPEC_TRY(layer(8, C3, A[D3A].g, C3, false, E4B, E3B));
     upcat_bwd(C3, E4B, E3B);
     TVSPEC_TRY(layer(7, E4A, A[E4B].g, E4A, true));
     TVSPEC_TRY(layer(6, P3, A[E4A].g, P3, false));
@@ -1977,7 +1968,10 @@ extern "C" int tvspec_net_create(int H, int W, int max_batch, unsigned long long
         a.W = W >> as[i].lvl;
         a.C = as[i].C;
         const size_t bytes = (size_t)max_batch * a.H * a.W * a.C * sizeof(__bf16);
-        int rc = net_alloc(n, (void **)&a.a, bytes);
+        // a concatenation is only ever read in place: it has a gradient but
+        // no stored activation
+        const bool cat = i == C3 || i == C2 || i == C1;
+        int rc = cat ? TVSPEC_OK : net_alloc(n, (void **)&a.a, bytes);
         if (rc == TVSPEC_OK)
             rc = net_alloc(n, (void **)&a.g, bytes);
         if (rc != TVSPEC_OK)
