@@ -416,6 +416,27 @@ template <typename S, typename M> TileKernel<S, M> narrow_tile_kernel(int t, int
     return k_chambolle_tile<S, M, kTileX, kNarrowY, 8, kNarrowThreads>;
 }
 
+// The whole-plane form: a plane of at most kPlaneMax x kPlaneMax pixels is
+// one tile whose region is the whole image (no halo, TB = 0), so one launch
+// runs every iteration of a solve: nothing outside the region feeds it, and
+// the region's pixels outside the image keep p = 0 as they do in the tiles.
+// LDS: three (64 + 2)^2 planes of the state type, 104.5 KB in float64 (the
+// 160 KB of a gfx950 CU); 4 pixels per thread.
+constexpr int kPlaneMax = 64;
+
+template <typename S, typename M> TileKernel<S, M> plane_kernel()
+{
+    return k_chambolle_tile<S, M, kPlaneMax, kPlaneMax, 0, kTileThreads>;
+}
+
+// Whether a step takes the whole-plane form: small planes, the Chambolle
+// solver, automatic blocking and the square tile option.
+bool whole_plane(const StepConfig &cfg)
+{
+    return cfg.solver != kSolverPDHG && cfg.iters_per_launch == 0 && cfg.tile == kTileShapeSquare &&
+           cfg.H <= kPlaneMax && cfg.W <= kPlaneMax;
+}
+
 // Smallest compiled halo width >= t.
 template <typename S, typename M> TileKernel<S, M> tile_kernel(int t, int *tb)
 {
@@ -531,10 +552,12 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
 {
     const int plane = cfg.H * cfg.W;
     const bool pd = cfg.solver == kSolverPDHG;
+    const bool whole = whole_plane(cfg);
     const bool narrow = !pd && cfg.tile == kTileShapeNarrow;
-    const int tile_y = narrow ? kNarrowY : kTileY;
+    const int tile_y = whole ? kPlaneMax : (narrow ? kNarrowY : kTileY);
+    const int tile_x = whole ? kPlaneMax : kTileX;
     const int threads = narrow ? kNarrowThreads : kTileThreads;
-    const int ntx = (cfg.W + kTileX - 1) / kTileX;
+    const int ntx = (cfg.W + tile_x - 1) / tile_x;
     const int nty = (cfg.H + tile_y - 1) / tile_y;
     const int ntiles = ntx * nty;
     int tb = 0;
@@ -544,11 +567,13 @@ template <typename S, typename M> int step_impl(const StepConfig &cfg, SlotDesc 
     PdhgKernel<S, M> kp = nullptr;
     if (pd)
         kp = pdhg_kernel<S, M>(want, &tb);
+    else if (whole)
+        kt = plane_kernel<S, M>();
     else if (narrow)
         kt = narrow_tile_kernel<S, M>(want, &tb);
     else
         kt = tile_kernel<S, M>(want, &tb);
-    const int per_launch = cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb;
+    const int per_launch = whole ? cfg.iters : (cfg.iters_per_launch > 0 ? cfg.iters_per_launch : tb);
     int cur = *parity;
 
     // timing: one event pair around the back-to-back Chambolle launches of
@@ -651,6 +676,8 @@ void slot_carve(SlotDesc &d, char *base, int precision, int solver, int H, int W
 
 int tile_launches_per_step(const StepConfig &cfg, int nslots)
 {
+    if (whole_plane(cfg))
+        return 1;
     const bool narrow = cfg.solver != kSolverPDHG && cfg.tile == kTileShapeNarrow;
     const int tile_y = narrow ? kNarrowY : kTileY;
     const int ntiles = ((cfg.W + kTileX - 1) / kTileX) * ((cfg.H + tile_y - 1) / tile_y);
