@@ -665,7 +665,10 @@ __device__ __forceinline__ bf16x8 tr_operand(const lds_u8 *p, int half)
     return __builtin_bit_cast(bf16x8, v);
 }
 
-template <int OW, int WC>
+// CAT: X is the concatenation [upsampled Xlow, X] of a decoder level, read in
+// place (a separate instantiation, so the other layers keep the registers
+// its addressing costs).
+template <int OW, int WC, bool CAT>
 __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dY,
                                                    float *__restrict__ part, size_t rs, int with_bias, int H, int W,
                                                    int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles,
@@ -753,10 +756,14 @@ __global__ __launch_bounds__(64 * WC, 2) void k_wgrad(const __bf16 *__restrict__
                 const int xx = x0 + pix - hr * kGHX - 1;
                 const int c = c0 + 8 * grp;
                 if (yy >= 0 && yy < H && xx >= 0 && xx < W && c < Cin) {
-                    if (c < Clow)  // the upsampled half of a concatenated input, read in place
-                        src = Xlow + ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow + c;
-                    else
-                        src = X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) + (c - Clow);
+                    if constexpr (CAT) {
+                        if (c < Clow)  // the upsampled half of the concatenation
+                            src = Xlow + ((size_t)((size_t)b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Clow + c;
+                        else
+                            src = X + ((size_t)((size_t)b * H + yy) * W + xx) * (Cin - Clow) + (c - Clow);
+                    } else {
+                        src = X + ((size_t)((size_t)b * H + yy) * W + xx) * Cin + c;
+                    }
                 }
             }
             vx[j] = *(const global_bf16x8 *)src;
@@ -1535,8 +1542,12 @@ void wgrad_launch(dim3 grid, const __bf16 *x, const __bf16 *dy, float *part, siz
                   int Cin, int Cout, int n_ct, int tiles_x, int tiles_y, int tiles, int tpr, const __bf16 *xlow,
                   int clow, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_wgrad<OW, WC>), grid, dim3(64 * WC), 0, st, x, dy, part, rs, with_bias, H, W, Cin, Cout,
-                       n_ct, tiles_x, tiles_y, tiles, tpr, xlow, clow);
+    if (xlow)
+        hipLaunchKernelGGL((k_wgrad<OW, WC, true>), grid, dim3(64 * WC), 0, st, x, dy, part, rs, with_bias, H, W,
+                           Cin, Cout, n_ct, tiles_x, tiles_y, tiles, tpr, xlow, clow);
+    else
+        hipLaunchKernelGGL((k_wgrad<OW, WC, false>), grid, dim3(64 * WC), 0, st, x, dy, part, rs, with_bias, H, W,
+                           Cin, Cout, n_ct, tiles_x, tiles_y, tiles, tpr, xlow, clow);
 }
 
 // Weight gradient [Cout][9][Cin] and, with out.db or out.flat, the bias
@@ -1770,29 +1781,33 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     // of its input masked by mask_in (the input's own ReLU) or unmasked
     // (a decoder level's first layer: `in` is the concatenation, whose
     // weight gradient reads the lower level `low` and the skip tensor `skip`
-    // in place)
+    // in place, and whose input gradient goes to the two sources: the skip
+    // channels straight into the skip tensor's gradient with its ReLU mask,
+    // the upsampled channels into the concatenation's gradient buffer, from
+    // which k_up_concat_bwd sums each 2 x 2 block into the lower level's)
     auto layer = [&](int li, int in, const __bf16 *dz, int din, bool mask_in, int low = -1, int skip = -1) -> int {
         const Layer &l = n->L[li];
         RowOut go;  // straight into the layer's slice of the flat gradient
         go.flat = n->grad + l.off;
         go.cout_r = l.cout_r;
         go.cin_r = l.cin_r;
-        if (low >= 0)
-            TVSPEC_TRY(conv_wgrad(wk, A[skip].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st, A[low].a,
-                                  A[low].C));
-        else
-            TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st));
+        if (low >= 0) {
+            const int cl = A[low].C, cs = A[skip].C;
+            TVSPEC_TRY(conv_wgrad(wk, A[skip].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st, A[low].a, cl));
+            TVSPEC_TRY(conv_fwd(dz, B, A[in].H, A[in].W, l.cout, l.wd + (size_t)cl * 9 * l.cout, nullptr, cs, 0,
+                                A[skip].a, A[skip].g, false, st));
+            TVSPEC_TRY(conv_fwd(dz, B, A[in].H, A[in].W, l.cout, l.wd, nullptr, cl, 0, nullptr, A[in].g, false, st));
+            const long long cnt = (long long)B * A[low].H * A[low].W * cl;
+            hipLaunchKernelGGL(k_up_concat_bwd, dim3(grid_for(cnt)), dim3(kT), 0, st, A[in].g, A[low].a, A[skip].a,
+                               A[low].g, A[skip].g, B, A[in].H, A[in].W, cl, 0);
+            return TVSPEC_OK;
+        }
+        TVSPEC_TRY(conv_wgrad(wk, A[in].a, dz, B, A[in].H, A[in].W, l.cin, l.cout, go, st));
         // input gradient: the forward kernel on the layer's flipped weights
         if (din >= 0)
             TVSPEC_TRY(conv_fwd(dz, B, A[in].H, A[in].W, l.cout, l.wd, nullptr, l.cin, 0,
                                 mask_in ? A[in].a : nullptr, A[din].g, false, st));
         return TVSPEC_OK;
-    };
-    auto upcat_bwd = [&](int cat, int low, int skip) {
-        const long long cnt = (long long)B * (A[low].H * A[low].W * (long long)A[low].C +
-                                              A[skip].H * A[skip].W * (long long)A[skip].C);
-        hipLaunchKernelGGL(k_up_concat_bwd, dim3(grid_for(cnt)), dim3(kT), 0, st, A[cat].g, A[low].a, A[skip].a,
-                           A[low].g, A[skip].g, B, A[cat].H, A[cat].W, A[low].C, A[skip].C);
     };
     auto pool_bwd = [&](int x, int p) {
         const long long cnt = (long long)B * A[p].H * A[p].W * A[p].C;
@@ -1802,13 +1817,10 @@ int backward(tvspec_net *n, int B, hipStream_t st)
     TVSPEC_TRY(layer(14, D1B, n->dout, D1B, true));
     TVSPEC_TRY(layer(13, D1A, A[D1B].g, D1A, true));
     TVSPEC_TRY(layer(12, C1, A[D1A].g, C1, false, D2B, E1B));
-    upcat_bwd(C1, D2B, E1B);
     TVSPEC_TRY(layer(11, D2A, A[D2B].g, D2A, true));
     TVSPEC_TRY(layer(10, C2, A[D2A].g, C2, false, D3B, E2B));
-    upcat_bwd(C2, D3B, E2B);
     TVSPEC_TRY(layer(9, D3A, A[D3B].g, D3A, true));
     TVSPEC_TRY(layer(8, C3, A[D3A].g, C3, false, E4B, E3B));
-    upcat_bwd(C3, E4B, E3B);
     TVSPEC_TRY(layer(7, E4A, A[E4B].g, E4A, true));
     TVSPEC_TRY(layer(6, P3, A[E4A].g, P3, false));
     pool_bwd(E3B, P3);

@@ -113,6 +113,21 @@ def test_launch_configuration_does_not_change_results(tv, precision, ts):
             assert np.array_equal(outs[0][k], o[k]), k
 
 
+@pytest.mark.parametrize("precision", ["mixed", "f64", "f32"])
+@pytest.mark.parametrize("C,H,W", [(2, 50, 37), (1, 64, 64), (3, 64, 17), (1, 2, 2)])
+def test_whole_plane_form_equals_tiles(tv, precision, C, H, W):
+    """Planes of at most 64 x 64 with automatic blocking run each ROF solve
+    in one launch over the whole plane; explicit blocking factors take the
+    tiles.  Same per-pixel arithmetic, so the results agree bit for bit."""
+    f = synth.shapes_image(synth.ShapeSpec(H, W, C, 4, size_lo=1, size_hi=max(2, min(H, W) // 3)), seed=H + W)
+    kw = dict(dt=0.01, K=6, iters=37, edges=[0, 1, 2, 6], precision=precision)
+    whole = gpu(tv, f, **kw)
+    for t in (5, 8):
+        o = gpu(tv, f, iters_per_launch=t, **kw)
+        for k in ("bands", "S", "residual", "stats"):
+            assert np.array_equal(whole[k], o[k]), (k, t)
+
+
 def test_channels_equal_separate_calls(tv):
     f = synth.shapes_image(synth.ShapeSpec(40, 56, 3, 6), seed=8)
     kw = dict(dt=0.01, K=8, iters=30, edges=[0, 1, 2, 4, 8])
