@@ -30,6 +30,10 @@ FLAGS = [
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-mcode-object-version=5",
+    # kernel arguments preloaded into scalar registers at dispatch (the
+    # code keeps a fallback entry that loads them on firmware without it):
+    # one memory round trip less before a kernel's first address is known
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall",
     # only the C ABI (TVSPEC_API in the header) is exported
     "-fvisibility=hidden",

@@ -119,8 +119,20 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
 {
     const int slot = blockIdx.y / C;
     const int chan = blockIdx.y - slot * C;
+    // Every descriptor field the launch uses is read before the activity
+    // test, so the loads go out together and the workgroup waits for one
+    // scalar-memory round trip instead of one per dependent use.
     const SlotDesc &sd = slots[slot];
-    if (!sd.active)
+    const int active = sd.active;
+    const int kc = sd.k_cur;
+    const void *v_pxi = sd.px[cur], *v_pyi = sd.py[cur];
+    void *v_pxo = sd.px[1 - cur], *v_pyo = sd.py[1 - cur];
+    const double *v_u0 = sd.u[0], *v_u1 = sd.u[1];
+    const void *v_gx = sd.gx, *v_gy = sd.gy;
+    const double dt = sd.dt;
+    asm volatile("" ::"s"(active), "s"(kc), "s"(v_pxi), "s"(v_pyi), "s"(v_pxo), "s"(v_pyo), "s"(v_u0), "s"(v_u1),
+                 "s"(v_gx), "s"(v_gy), "s"(dt));
+    if (!active)
         return;
     constexpr bool kW = std::is_same<S, double>::value; // w-form data term
     constexpr int RX = BX + 2 * TB;
@@ -136,14 +148,13 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
 
     const size_t plane = (size_t)H * (size_t)W;
     const size_t coff = (size_t)chan * plane;
-    const S *__restrict__ pxi = (const S *)sd.px[cur] + coff;
-    const S *__restrict__ pyi = (const S *)sd.py[cur] + coff;
-    const double *__restrict__ ui = sd.u[sd.k_cur & 1] + coff;
-    const M *__restrict__ gxi = (const M *)sd.gx + coff;
-    const M *__restrict__ gyi = (const M *)sd.gy + coff;
-    S *__restrict__ pxo = (S *)sd.px[1 - cur] + coff;
-    S *__restrict__ pyo = (S *)sd.py[1 - cur] + coff;
-    const double dt = sd.dt;
+    const S *__restrict__ pxi = (const S *)v_pxi + coff;
+    const S *__restrict__ pyi = (const S *)v_pyi + coff;
+    const double *__restrict__ ui = ((kc & 1) ? v_u1 : v_u0) + coff;
+    const M *__restrict__ gxi = (const M *)v_gx + coff;
+    const M *__restrict__ gyi = (const M *)v_gy + coff;
+    S *__restrict__ pxo = (S *)v_pxo + coff;
+    S *__restrict__ pyo = (S *)v_pyo + coff;
     const double idt = 1.0 / dt;
 
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs,
@@ -177,10 +188,17 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
     int rr[PPT];     // region row of the pixel (RY + 1 for the idle lanes of the last pass)
     S mx[PPT];       // 1 where a_x is live (inside the image, not its last column), else 0
     S my[PPT];       // 1 where a_y is live (inside the image, not its last row), else 0
+    // Region load.  Every pixel's loads are issued before any loaded value
+    // is used (the scaling and the LDS stores come in a second pass), so the
+    // workgroup waits for one memory round trip rather than one per pixel.
+    double uq[PPT];  // u_k (w-form) of the pixel, raw
+    M g1[PPT], g2[PPT]; // Gx, Gy (gradient form), raw
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int idx = threadIdx.x + m * NT;
-        S vx = S(0), vy = S(0), vq = S(0), vgy = S(0);
+        S vx = S(0), vy = S(0);
+        double vu = 0.0;
+        M vg1 = M(0), vg2 = M(0);
         bool ax_live = false, ay_live = false;
         int l = 0;
         rr[m] = RY + 1;
@@ -198,28 +216,41 @@ __global__ __launch_bounds__(NT) void k_chambolle_tile(const SlotDesc *__restric
                     vy = pyi[q];
                 }
                 if constexpr (kW) {
-                    if constexpr (std::is_same<M, double>::value)
-                        vq = ui[q] / dt;
-                    else
-                        vq = ui[q] * idt;
+                    vu = ui[q];
                 } else {
-                    vq = (S)gxi[q];
-                    vgy = (S)gyi[q];
+                    vg1 = gxi[q];
+                    vg2 = gyi[q];
                 }
                 ax_live = gj < W - 1;
                 ay_live = gi < H - 1;
             }
-            s_px[l] = vx;
-            s_py[l] = vy;
         }
         li[m] = l;
         px[m] = vx;
         py[m] = vy;
-        gq[m] = vq;
-        gy[m] = vgy;
+        uq[m] = vu;
+        g1[m] = vg1;
+        g2[m] = vg2;
         d[m] = S(0);
         mx[m] = ax_live ? S(1) : S(0);
         my[m] = ay_live ? S(1) : S(0);
+    }
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        if constexpr (kW) {
+            if constexpr (std::is_same<M, double>::value)
+                gq[m] = uq[m] / dt;
+            else
+                gq[m] = uq[m] * idt;
+            gy[m] = S(0);
+        } else {
+            gq[m] = (S)g1[m];
+            gy[m] = (S)g2[m];
+        }
+        if (m < PPT - 1 || threadIdx.x + m * NT < RN) {
+            s_px[li[m]] = px[m];
+            s_py[li[m]] = py[m];
+        }
     }
     __syncthreads();
 
@@ -322,8 +353,18 @@ __global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ s
 {
     const int slot = blockIdx.y / C;
     const int chan = blockIdx.y - slot * C;
+    // descriptor fields read together before the activity test, as in
+    // k_chambolle_tile
     const SlotDesc &sd = slots[slot];
-    if (!sd.active)
+    const int active = sd.active;
+    const int kc = sd.k_cur;
+    const void *v_xi = sd.x[cur], *v_xbi = sd.xb[cur], *v_yxi = sd.px[cur], *v_yyi = sd.py[cur];
+    void *v_xo = sd.x[1 - cur], *v_xbo = sd.xb[1 - cur], *v_yxo = sd.px[1 - cur], *v_yyo = sd.py[1 - cur];
+    const double *v_u0 = sd.u[0], *v_u1 = sd.u[1];
+    const double dt = sd.dt;
+    asm volatile("" ::"s"(active), "s"(kc), "s"(v_xi), "s"(v_xbi), "s"(v_yxi), "s"(v_yyi), "s"(v_xo), "s"(v_xbo),
+                 "s"(v_yxo), "s"(v_yyo), "s"(v_u0), "s"(v_u1), "s"(dt));
+    if (!active)
         return;
     constexpr int RX = BX + 2 * TB;
     constexpr int RY = BY + 2 * TB;
@@ -338,16 +379,16 @@ __global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ s
 
     const size_t plane = (size_t)H * (size_t)W;
     const size_t coff = (size_t)chan * plane;
-    const S lam = (S)sd.dt;
-    const double *__restrict__ g = sd.u[sd.k_cur & 1] + coff;
-    const S *__restrict__ xi = (const S *)sd.x[cur] + coff;
-    const S *__restrict__ xbi = (const S *)sd.xb[cur] + coff;
-    const S *__restrict__ yxi = (const S *)sd.px[cur] + coff;
-    const S *__restrict__ yyi = (const S *)sd.py[cur] + coff;
-    S *__restrict__ xo = (S *)sd.x[1 - cur] + coff;
-    S *__restrict__ xbo = (S *)sd.xb[1 - cur] + coff;
-    S *__restrict__ yxo = (S *)sd.px[1 - cur] + coff;
-    S *__restrict__ yyo = (S *)sd.py[1 - cur] + coff;
+    const S lam = (S)dt;
+    const double *__restrict__ g = ((kc & 1) ? v_u1 : v_u0) + coff;
+    const S *__restrict__ xi = (const S *)v_xi + coff;
+    const S *__restrict__ xbi = (const S *)v_xbi + coff;
+    const S *__restrict__ yxi = (const S *)v_yxi + coff;
+    const S *__restrict__ yyi = (const S *)v_yyi + coff;
+    S *__restrict__ xo = (S *)v_xo + coff;
+    S *__restrict__ xbo = (S *)v_xbo + coff;
+    S *__restrict__ yxo = (S *)v_yxo + coff;
+    S *__restrict__ yyo = (S *)v_yyo + coff;
 
     const int b = blockIdx.x;
     const int L = ((ntiles & 7) == 0) ? (b & 7) * (ntiles >> 3) + (b >> 3) : b;
@@ -372,12 +413,15 @@ __global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ s
     }
 
     S x[PPT], xb[PPT], yx[PPT], yy[PPT], gg[PPT], mx[PPT], my[PPT];
+    double graw[PPT];
     int li[PPT];
     int rr[PPT];     // region row of the pixel (RY + 1 for the idle lanes of the last pass)
+    // region load: all loads first, their uses in a second pass
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int idx = threadIdx.x + m * NT;
-        S vx = S(0), vxb = S(0), vyx = S(0), vyy = S(0), vg = S(0);
+        S vx = S(0), vxb = S(0), vyx = S(0), vyy = S(0);
+        double vg = 0.0;
         bool ax_live = false, ay_live = false;
         int l = 0;
         rr[m] = RY + 1;
@@ -390,11 +434,8 @@ __global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ s
             rr[m] = ri;
             if (gi >= 0 && gi < H && gj >= 0 && gj < W) {
                 const size_t q = (size_t)gi * W + gj;
-                vg = (S)g[q];
-                if (solve_start) {
-                    vx = vg;
-                    vxb = vg;
-                } else {
+                vg = g[q];
+                if (!solve_start) {
                     vx = xi[q];
                     vxb = xbi[q];
                 }
@@ -405,16 +446,25 @@ __global__ __launch_bounds__(NT) void k_pdhg_tile(const SlotDesc *__restrict__ s
                 ax_live = gj < W - 1;
                 ay_live = gi < H - 1;
             }
-            s_xb[l] = vxb;
         }
         li[m] = l;
         x[m] = vx;
         xb[m] = vxb;
         yx[m] = vyx;
         yy[m] = vyy;
-        gg[m] = vg;
+        graw[m] = vg;
         mx[m] = ax_live ? S(1) : S(0);
         my[m] = ay_live ? S(1) : S(0);
+    }
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        gg[m] = (S)graw[m];
+        if (solve_start) {
+            x[m] = gg[m];
+            xb[m] = gg[m];
+        }
+        if (m < PPT - 1 || threadIdx.x + m * NT < RN)
+            s_xb[li[m]] = xb[m];
     }
     __syncthreads();
 
