@@ -374,6 +374,27 @@ def test_batch_equals_separate_calls(tv, orc):
         check_parity({k: v.cpu().numpy() for k, v in outs[b].items()}, r)
 
 
+@pytest.mark.slow
+def test_batched_64_workload_as_benchmarked(tv, orc):
+    """The batched 64x64 workload in the configuration the benchmark times
+    (256 seeded shape images in one call, dt 0.005, K 60, 200 iterations,
+    4 dyadic bands; each plane one workgroup, one launch per ROF solve):
+    every image's identity and mean drift to float64 round-off, and three
+    sampled images (first, middle, last) against the oracle's full runs."""
+    n = 256
+    imgs = np.stack([synth.shapes_image(synth.SMALL_64, 1000 + i) for i in range(n)])
+    edges = [0, 1, 2, 4, 60]
+    ft = torch.from_numpy(imgs).to("cuda:0")
+    print("batched 64x64 workload: 256 images, K 60, 200 iterations", flush=True)
+    outs = tv.tvspec_decompose_batch_dev(ft, [0.005] * n, [60] * n, 200, [edges] * n)
+    torch.cuda.synchronize()
+    st = torch.stack([o["stats"] for o in outs]).cpu().numpy()
+    assert (st[:, 0] <= 1e-12).all() and (st[:, 1] <= 1e-12).all() and (st[:, 2] == 0).all()
+    for b in (0, n // 2, n - 1):
+        r = orc.decompose(imgs[b], 0.005, 60, 200, edges)
+        check_parity({k: v.cpu().numpy() for k, v in outs[b].items()}, r)
+
+
 def test_batch_validation(tv):
     ft = torch.zeros((2, 1, 8, 8), device="cuda:0")
     with pytest.raises(tv.TvspecError) as ei:
