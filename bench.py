@@ -271,6 +271,37 @@ def pdhg_block(f, wl, edges, precision, steps):
             "report": {"recon_err": float(st[0]), "mean_err": float(st[1])}}
 
 
+def other_precisions(f, wl, edges, ref, steps=2):
+    """The same workload in the other two precision modes of the inner
+    iteration: time per decomposition (one untimed call, then `steps` back
+    to back) and the distance of the bands and S from the reference output
+    (the headline mode's; its own distance from the float64 oracle is
+    asserted by the GPU tests)."""
+    import torch
+    from paper_2006_10004_amd import tvspec
+    res = {}
+    for prec in ("f32", "mixed", "f64"):
+        if prec == wl["precision"]:
+            continue
+
+        def run(out=None):
+            return tvspec.tvspec_decompose_dev(f, wl["dt"], wl["K"], wl["inner_iters"], edges, out=out,
+                                               tau=wl["tau"], precision=prec)
+
+        out = run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run(out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        px = wl["H"] * wl["W"] * wl["C"]
+        res[prec] = {"ms_per_step": ms, "MPix_per_s": px / 1e6 / (ms / 1e3), "dtype": DTYPE[prec],
+                     "bands_max_abs_vs_headline": float((out["bands"] - ref["bands"]).abs().max()),
+                     "S_rel_peak_vs_headline": float((out["S"] - ref["S"]).abs().max() / ref["S"].abs().max())}
+    return res
+
+
 def batch_throughput(n, precision):
     """One batched call over n seeded 64x64 shape images (dt 0.005, K 60, 200
     iterations, 4 dyadic bands): MPix/s of the whole batch."""
@@ -728,6 +759,8 @@ def main():
                          "(batch 16 of 3x256x256) and print that record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip timing the workload in the other two precision modes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 4 plain device copies of MIB MiB each "
                          "(reference dispatches for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -846,6 +879,10 @@ def main():
     if args.pdhg_steps > 0:
         rec["pdhg"] = pdhg_block(f, wl, edges, args.precision, args.pdhg_steps)
         print("bench: primal-dual pass done", file=sys.stderr, flush=True)
+
+    if not args.no_precisions:
+        rec["precisions"] = other_precisions(f, wl, edges, out)
+        print("bench: other precision modes done", file=sys.stderr, flush=True)
 
     if args.batch_images > 0:
         rec["batch_64x64"] = batch_throughput(args.batch_images, args.precision)
