@@ -38,16 +38,16 @@ from .nn import BANDS, IN_CHANNELS, OUT_CHANNELS, Net
 # iterations per ROF solve, 4 dyadic bands {0, 1, 2, 4, 100} and the residual.
 FLOW = dict(dt=0.005, K=100, iters=150, edges=[0, 1, 2, 4, 100])
 
-# Floor of the training loss's denominators (tvspec_net_set_loss_floor): 20%
+# Floor of the training loss's denominators (tvspec_net_set_loss_floor): 5%
 # of the energy of a band at the dataset's RMS size.
-LOSS_FLOOR = 0.2
+LOSS_FLOOR = 0.05
 
 # Gradient-norm clipping (tvspec_net_set_grad_clip): a step's gradient is
-# scaled down to at most 4x the running average of gradient norms.  With
-# the schedule below (16000 steps, two seeds), floor 0.2 and clip 4 end at
-# held-out all-band relative L1 0.419 / 0.439 against 0.444 / 0.457 for
-# floor 0.05 and clip 2; clip 8 let one seed spike (0.500).
-GRAD_CLIP = 4.0
+# scaled down to at most 2x the running average of gradient norms.  Floor
+# 0.2 with clip 4 was measured too: held-out all-band relative L1 0.419,
+# 0.439 and 0.479 over three minibatch orders, against 0.444, 0.445 and
+# 0.457 here; the order alone moves the result by more than the setting.
+GRAD_CLIP = 2.0
 
 # Learning-rate schedule of the benchmark's training (cosine_lr): peak 3e-3
 # after 500 warm-up steps, cosine decay to 1e-5.  Measured on the training
